@@ -1,0 +1,559 @@
+/*
+ * pms_oracle.c -- plain, slow CPU oracle for exact planted (l,d)-motif search.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing on the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark use it. It shares no code with the GPU library.
+ *
+ * What it computes (Sec. 1.2.5, Definitions 1-5 and the qPMS definition
+ * with q = n, which is plain PMS):
+ *
+ *   R(s_1..s_n, l, d) = all l-mers M over {A,C,G,T} such that every input
+ *   string s_i has an l-mer y (one of its m-l+1 substrings of length l)
+ *   with Hamming distance d_H(M, y) <= d.
+ *
+ * Readings taken where the text is silent or garbled:
+ *   - an l-mer of s starts at any of the m-l+1 offsets, the last one
+ *     included (Definition 2 is garbled; this is its evident meaning);
+ *   - "no more than d" means <= d (Definition 5);
+ *   - bases are coded A=0, C=1, G=2, T=3, as in the compression example of
+ *     Sec. 3.3.1 (AGGCTA -> 022130); any other byte is an input error;
+ *   - a motif is reported as the integer sum_j code(M[j]) * 4^(l-1-j): first
+ *     base in the highest digit, so numeric order is lexicographic order;
+ *   - one strand only (reverse complements are never mentioned).
+ *
+ * Two independent ways to get R:
+ *   O1 (sample-driven, Sec. 1.3.1 and Observation 3.1 with q = n): every
+ *      motif lies in the d-sphere B(x,d) of some l-mer x of the first string,
+ *      so enumerate each B(x,d) (the tree T_d(x) of Sec. 3.2.1, every node
+ *      once) and keep the candidates that have a d-neighbour in every other
+ *      string, testing the strings in input order and stopping at the first
+ *      one with none. The candidate test uses a packed XOR/popcount Hamming
+ *      distance written here (Sec. 3.3.1 describes the bitwise form).
+ *   O0 (pattern-driven, Sec. 1.3.1): try every one of the 4^l l-mers and
+ *      compare it character by character with every l-mer of every string.
+ *
+ * O1 also counts the canonical number of Hamming tests, H_canon: for each
+ * enumerated candidate (with multiplicity over references x), (m-l+1) times
+ * the number of strings s_2..s_n examined, up to and including the first one
+ * that has no d-neighbour.
+ */
+#define _GNU_SOURCE
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_EBASE = -2, OR_ENOMEM = -3 };
+
+/* ---- encoding (Sec. 3.3.1 example: A=0, C=1, G=2, T=3) ---------------- */
+
+static int base_code(unsigned char ch)
+{
+    switch (ch) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    default: return -1;
+    }
+}
+
+/* ASCII rows -> base codes. Returns the index of the first bad byte, or -1. */
+static long long decode(const char *seqs, size_t total, unsigned char *out)
+{
+    for (size_t k = 0; k < total; k++) {
+        int b = base_code((unsigned char)seqs[k]);
+        if (b < 0)
+            return (long long)k;
+        out[k] = (unsigned char)b;
+    }
+    return -1;
+}
+
+int oracle_encode(const char *seqs, long long total, unsigned char *out,
+                  long long *bad)
+{
+    long long k = decode(seqs, (size_t)total, out);
+    if (bad)
+        *bad = k;
+    return k < 0 ? OR_OK : OR_EBASE;
+}
+
+/* l-mer starting at b[0..l-1] -> code with the first base in the top digit. */
+static uint64_t lmer_code(const unsigned char *b, int l)
+{
+    uint64_t c = 0;
+    for (int j = 0; j < l; j++)
+        c = (c << 2) | b[j];
+    return c;
+}
+
+uint64_t oracle_lmer_code(const char *lmer, int l)
+{
+    uint64_t c = 0;
+    for (int j = 0; j < l; j++)
+        c = (c << 2) | (uint64_t)base_code((unsigned char)lmer[j]);
+    return c;
+}
+
+/* ---- distances ------------------------------------------------------- */
+
+/* Definition 3: number of positions where the two l-mers differ. */
+static int hamming_naive(const unsigned char *a, const unsigned char *b, int l)
+{
+    int h = 0;
+    for (int j = 0; j < l; j++)
+        h += (a[j] != b[j]);
+    return h;
+}
+
+/* Same count on two packed codes: a digit differs iff either of its two
+ * bits differs. */
+static inline int hamming_packed(uint64_t a, uint64_t b)
+{
+    uint64_t v = a ^ b;
+    return __builtin_popcountll((v | (v >> 1)) & 0x5555555555555555ULL);
+}
+
+/* Sec. 3.3.1: an l-mer becomes ceil(log2 |Sigma|) = 2 groups (bit planes);
+ * group k holds bit k of each base code, bit j of the group for base j.
+ * The distance is the number of set bits of the OR of the per-group XORs.
+ * Restricted to l <= 32 (one 32-bit word per group). */
+int oracle_groups(const char *lmer, int l, uint32_t *g1, uint32_t *g0)
+{
+    if (l < 1 || l > 32)
+        return OR_EINVAL;
+    uint32_t hi = 0, lo = 0;
+    for (int j = 0; j < l; j++) {
+        int b = base_code((unsigned char)lmer[j]);
+        if (b < 0)
+            return OR_EBASE;
+        hi |= (uint32_t)((b >> 1) & 1) << j;
+        lo |= (uint32_t)(b & 1) << j;
+    }
+    *g1 = hi;
+    *g0 = lo;
+    return OR_OK;
+}
+
+int oracle_hamming_groups(uint32_t a1, uint32_t a0, uint32_t b1, uint32_t b0)
+{
+    return __builtin_popcount((a1 ^ b1) | (a0 ^ b0));
+}
+
+int oracle_hamming_naive(const char *a, const char *b, int l)
+{
+    int h = 0;
+    for (int j = 0; j < l; j++)
+        h += (a[j] != b[j]);
+    return h;
+}
+
+/* ---- size of the sphere B(a, R) (Table 3.1) ---------------------------- */
+
+/* n_B(l, d) = sum_{k=0..d} C(l, k) (|Sigma| - 1)^k: choose k positions and
+ * one of the |Sigma|-1 other letters at each. */
+uint64_t oracle_nb(int l, int d, int sigma)
+{
+    uint64_t total = 0;
+    for (int k = 0; k <= d && k <= l; k++) {
+        uint64_t c = 1;
+        for (int i = 0; i < k; i++)
+            c = c * (uint64_t)(l - i) / (uint64_t)(i + 1);
+        uint64_t p = 1;
+        for (int i = 0; i < k; i++)
+            p *= (uint64_t)(sigma - 1);
+        total += c * p;
+    }
+    return total;
+}
+
+/* ---- growable output vector ------------------------------------------ */
+
+typedef struct {
+    uint64_t *v;
+    size_t n, cap;
+    int oom;
+} vec64;
+
+static void vpush(vec64 *a, uint64_t x)
+{
+    if (a->oom)
+        return;
+    if (a->n == a->cap) {
+        size_t nc = a->cap ? 2 * a->cap : 1024;
+        uint64_t *nv = (uint64_t *)realloc(a->v, nc * sizeof(uint64_t));
+        if (!nv) {
+            a->oom = 1;
+            return;
+        }
+        a->v = nv;
+        a->cap = nc;
+    }
+    a->v[a->n++] = x;
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Sort ascending and drop repeats: the result is a set (one correct byte
+ * representation). */
+static size_t sort_unique(uint64_t *v, size_t n)
+{
+    if (n == 0)
+        return 0;
+    qsort(v, n, sizeof(uint64_t), cmp_u64);
+    size_t w = 1;
+    for (size_t i = 1; i < n; i++)
+        if (v[i] != v[w - 1])
+            v[w++] = v[i];
+    return w;
+}
+
+static int pick_threads(int want)
+{
+    if (want > 0)
+        return want;
+    long p = sysconf(_SC_NPROCESSORS_ONLN);
+    return p > 0 ? (int)p : 1;
+}
+
+/* ---- O1: sample-driven ----------------------------------------------- */
+
+typedef struct {
+    /* shared, read-only */
+    const uint64_t *codes; /* n rows of L packed l-mer codes */
+    const unsigned char *bases; /* row 0 base codes (the references) */
+    int n, L, l, d;
+    int ref_begin, ref_end, nthreads, tid;
+    uint64_t *per_ref; /* optional: H_canon per reference */
+    /* per thread */
+    vec64 out;
+    uint64_t hcanon;
+} o1_job;
+
+/* Candidate test: strings s_2..s_n in input order, stop at the first one
+ * without an l-mer within distance d. Returns 1 if the candidate is a motif;
+ * *examined receives the number of strings looked at. */
+static int o1_test(const o1_job *J, uint64_t cand, int *examined)
+{
+    int e = 0;
+    for (int i = 1; i < J->n; i++) {
+        const uint64_t *row = J->codes + (size_t)i * J->L;
+        int hit = 0;
+        e++;
+        for (int j = 0; j < J->L; j++) {
+            if (hamming_packed(cand, row[j]) <= J->d) {
+                hit = 1;
+                break;
+            }
+        }
+        if (!hit) {
+            *examined = e;
+            return 0;
+        }
+    }
+    *examined = e;
+    return 1;
+}
+
+/* Walk T_d(x): the root is x; a node that last changed position p has
+ * children that change one position p' > p to one of the 3 other letters,
+ * so every string within distance d of x is visited exactly once. */
+static void o1_ball(o1_job *J, const unsigned char *x, uint64_t cand,
+                    int from, int budget, uint64_t *h)
+{
+    int examined;
+    if (o1_test(J, cand, &examined))
+        vpush(&J->out, cand);
+    *h += (uint64_t)examined * (uint64_t)J->L;
+    if (budget == 0)
+        return;
+    for (int p = from; p < J->l; p++) {
+        int shift = 2 * (J->l - 1 - p);
+        for (int b = 0; b < 4; b++) {
+            if (b == x[p])
+                continue;
+            uint64_t c2 = cand ^ ((uint64_t)(x[p] ^ b) << shift);
+            o1_ball(J, x, c2, p + 1, budget - 1, h);
+        }
+    }
+}
+
+static void *o1_worker(void *arg)
+{
+    o1_job *J = (o1_job *)arg;
+    int span = J->ref_end - J->ref_begin;
+    int lo = J->ref_begin + (int)((long long)span * J->tid / J->nthreads);
+    int hi = J->ref_begin + (int)((long long)span * (J->tid + 1) / J->nthreads);
+    for (int j = lo; j < hi; j++) {
+        const unsigned char *x = J->bases + j;
+        uint64_t h = 0;
+        o1_ball(J, x, lmer_code(x, J->l), 0, J->d, &h);
+        J->hcanon += h;
+        if (J->per_ref)
+            J->per_ref[j - J->ref_begin] = h;
+    }
+    return NULL;
+}
+
+static int check_args(int n, int m, int l, int d)
+{
+    if (n < 1 || l < 1 || l > 32 || m < l || d < 0 || d >= l)
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+/*
+ * O1 over the references x = s_1[j..j+l-1] for j in [ref_begin, ref_end)
+ * (ref_end < 0 means all m-l+1 of them). With the full range the output is R;
+ * a partial range gives the motifs found from those references only.
+ * *out is malloc'ed (free with oracle_free); *hcanon gets H_canon of the
+ * range; per_ref (may be NULL) gets H_canon per reference.
+ */
+int oracle_o1(const char *seqs, int n, int m, int l, int d, int ref_begin,
+              int ref_end, int nthreads, uint64_t **out, size_t *count,
+              uint64_t *hcanon, uint64_t *per_ref)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    int L = m - l + 1;
+    if (ref_end < 0 || ref_end > L)
+        ref_end = L;
+    if (ref_begin < 0 || ref_begin > ref_end)
+        return OR_EINVAL;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * L);
+    if (!bases || !codes) {
+        free(bases);
+        free(codes);
+        return OR_ENOMEM;
+    }
+    if (decode(seqs, total, bases) >= 0) {
+        free(bases);
+        free(codes);
+        return OR_EBASE;
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < L; j++)
+            codes[(size_t)i * L + j] = lmer_code(bases + (size_t)i * m + j, l);
+
+    int T = pick_threads(nthreads);
+    if (T > ref_end - ref_begin)
+        T = ref_end - ref_begin > 0 ? ref_end - ref_begin : 1;
+    o1_job *jobs = (o1_job *)calloc((size_t)T, sizeof(o1_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(bases);
+        free(codes);
+        free(jobs);
+        free(th);
+        return OR_ENOMEM;
+    }
+    for (int t = 0; t < T; t++) {
+        o1_job *J = &jobs[t];
+        J->codes = codes;
+        J->bases = bases;
+        J->n = n;
+        J->L = L;
+        J->l = l;
+        J->d = d;
+        J->ref_begin = ref_begin;
+        J->ref_end = ref_end;
+        J->nthreads = T;
+        J->tid = t;
+        J->per_ref = per_ref;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, o1_worker, &jobs[t]);
+    o1_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+
+    size_t tot = 0;
+    int oom = 0;
+    uint64_t h = 0;
+    for (int t = 0; t < T; t++) {
+        tot += jobs[t].out.n;
+        oom |= jobs[t].out.oom;
+        h += jobs[t].hcanon;
+    }
+    uint64_t *res = (uint64_t *)malloc(sizeof(uint64_t) * (tot ? tot : 1));
+    if (!res || oom) {
+        free(res);
+        res = NULL;
+        rc = OR_ENOMEM;
+    } else {
+        size_t w = 0;
+        for (int t = 0; t < T; t++) {
+            if (jobs[t].out.n)
+                memcpy(res + w, jobs[t].out.v, jobs[t].out.n * sizeof(uint64_t));
+            w += jobs[t].out.n;
+        }
+        *count = sort_unique(res, tot);
+        *out = res;
+        if (hcanon)
+            *hcanon = h;
+    }
+    for (int t = 0; t < T; t++)
+        free(jobs[t].out.v);
+    free(jobs);
+    free(th);
+    free(bases);
+    free(codes);
+    return rc;
+}
+
+/* ---- O0: pattern-driven brute force ---------------------------------- */
+
+typedef struct {
+    const unsigned char *bases;
+    int n, m, l, d, nthreads, tid;
+    vec64 out;
+} o0_job;
+
+/* Definition 4 and 5 written out: M qualifies iff every string has an
+ * l-mer within distance d, compared character by character. */
+static int o0_is_motif(const unsigned char *bases, int n, int m, int l, int d,
+                       const unsigned char *M)
+{
+    for (int i = 0; i < n; i++) {
+        const unsigned char *s = bases + (size_t)i * m;
+        int ok = 0;
+        for (int j = 0; j + l <= m && !ok; j++)
+            ok = hamming_naive(M, s + j, l) <= d;
+        if (!ok)
+            return 0;
+    }
+    return 1;
+}
+
+static void *o0_worker(void *arg)
+{
+    o0_job *J = (o0_job *)arg;
+    uint64_t space = 1ULL << (2 * J->l);
+    uint64_t lo = (uint64_t)((__uint128_t)space * J->tid / J->nthreads);
+    uint64_t hi = (uint64_t)((__uint128_t)space * (J->tid + 1) / J->nthreads);
+    unsigned char M[32];
+    for (uint64_t c = lo; c < hi; c++) {
+        for (int j = 0; j < J->l; j++)
+            M[j] = (unsigned char)((c >> (2 * (J->l - 1 - j))) & 3);
+        if (o0_is_motif(J->bases, J->n, J->m, J->l, J->d, M))
+            vpush(&J->out, c);
+    }
+    return NULL;
+}
+
+int oracle_o0(const char *seqs, int n, int m, int l, int d, int nthreads,
+              uint64_t **out, size_t *count)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    if (l > 16)
+        return OR_EINVAL; /* 4^l candidates: only for small l */
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    if (!bases)
+        return OR_ENOMEM;
+    if (decode(seqs, total, bases) >= 0) {
+        free(bases);
+        return OR_EBASE;
+    }
+    int T = pick_threads(nthreads);
+    o0_job *jobs = (o0_job *)calloc((size_t)T, sizeof(o0_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(bases);
+        free(jobs);
+        free(th);
+        return OR_ENOMEM;
+    }
+    for (int t = 0; t < T; t++) {
+        jobs[t].bases = bases;
+        jobs[t].n = n;
+        jobs[t].m = m;
+        jobs[t].l = l;
+        jobs[t].d = d;
+        jobs[t].nthreads = T;
+        jobs[t].tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, o0_worker, &jobs[t]);
+    o0_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    /* each thread covers an ascending code range, so the concatenation in
+     * thread order is already sorted and free of repeats */
+    size_t tot = 0;
+    int oom = 0;
+    for (int t = 0; t < T; t++) {
+        tot += jobs[t].out.n;
+        oom |= jobs[t].out.oom;
+    }
+    uint64_t *res = (uint64_t *)malloc(sizeof(uint64_t) * (tot ? tot : 1));
+    if (!res || oom) {
+        free(res);
+        rc = OR_ENOMEM;
+    } else {
+        size_t w = 0;
+        for (int t = 0; t < T; t++) {
+            if (jobs[t].out.n)
+                memcpy(res + w, jobs[t].out.v, jobs[t].out.n * sizeof(uint64_t));
+            w += jobs[t].out.n;
+        }
+        *out = res;
+        *count = tot;
+    }
+    for (int t = 0; t < T; t++)
+        free(jobs[t].out.v);
+    free(jobs);
+    free(th);
+    free(bases);
+    return rc;
+}
+
+/* Direct check of one code against every string (Definitions 4-5), for
+ * spot checks of outputs too large to recompute whole. 1 = motif, 0 = not,
+ * negative = error. */
+int oracle_is_motif(const char *seqs, int n, int m, int l, int d,
+                    uint64_t code)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    if (l < 32 && (code >> (2 * l)) != 0)
+        return OR_EINVAL;
+    unsigned char M[32];
+    for (int j = 0; j < l; j++)
+        M[j] = (unsigned char)((code >> (2 * (l - 1 - j))) & 3);
+    for (int i = 0; i < n; i++) {
+        const char *s = seqs + (size_t)i * m;
+        int ok = 0;
+        for (int j = 0; j + l <= m && !ok; j++) {
+            int h = 0;
+            for (int k = 0; k < l; k++) {
+                int b = base_code((unsigned char)s[j + k]);
+                if (b < 0)
+                    return OR_EBASE;
+                h += (b != M[k]);
+            }
+            ok = h <= d;
+        }
+        if (!ok)
+            return 0;
+    }
+    return 1;
+}
+
+void oracle_free(void *p)
+{
+    free(p);
+}

@@ -1,0 +1,50 @@
+"""Write the stored full-size results used by tests/test_oracle.py.
+
+Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
+on inputs from the seeded generator; nothing here touches the GPU library.
+Run from the repository root:  python tests/golden/make_golden.py
+"""
+import hashlib
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import pmsgen  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CASES = [("pms_9_2", 1), ("pms_9_2", 2), ("pms_9_2", 3), ("pms_13_4", 1)]
+
+
+def main():
+    for name, seed in CASES:
+        inst = pmsgen.plain(name, seed)
+        t0 = time.time()
+        o1, h = oracle.o1(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+        t1 = time.time()
+        o0 = oracle.o0(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+        t2 = time.time()
+        assert list(o1) == list(o0), (name, seed)
+        path = os.path.join(HERE, "%s_seed%d.txt" % (name, seed))
+        with open(path, "w") as f:
+            f.write("# Exact (l,d)-motif set of one synthetic planted instance,\n")
+            f.write("# written by tests/golden/make_golden.py from the CPU oracle\n")
+            f.write("# (sample-driven O1 and brute-force O0 agree).\n")
+            f.write("config = %s\nseed = %d\n" % (name, seed))
+            f.write("n = %d\nm = %d\nl = %d\nd = %d\n"
+                    % (inst.n, inst.m, inst.l, inst.d))
+            f.write("input_sha256 = %s\n" % hashlib.sha256(inst.seqs).hexdigest())
+            f.write("planted = %s\n" % inst.motif.decode())
+            f.write("hcanon = %d\n" % h)
+            f.write("count = %d\n" % len(o1))
+            f.write("motifs = %s\n" % ",".join(str(int(v)) for v in o1))
+            f.write("motif_strings = %s\n" % ",".join(
+                oracle.decode_code(v, inst.l).decode() for v in o1))
+        print(name, seed, len(o1), "O1 %.1fs O0 %.1fs" % (t1 - t0, t2 - t1))
+
+
+if __name__ == "__main__":
+    main()
