@@ -1,0 +1,238 @@
+/*
+ * pms.h -- C ABI of libpms: exact planted (l,d)-motif search on one MI355X.
+ *
+ * The operation (Definitions 1-5 of Sec. 1.2.5 and the qPMS definition with
+ * q = n, i.e. plain PMS): given n strings s_1..s_n of length m over
+ * {A,C,G,T}, return every l-mer M such that each s_i contains an l-mer y
+ * (any of its m-l+1 substrings of length l) with Hamming distance
+ * d_H(M, y) <= d (Definition 3: the number of mismatching positions).
+ *
+ * Result encoding. A motif M[0..l-1] is returned as the uint64
+ *     code(M) = sum_j b(M[j]) * 4^(l-1-j),  b(A)=0, b(C)=1, b(G)=2, b(T)=3
+ * (the base coding of the compression example in Sec. 3.3.1; first base in
+ * the most significant digit, so numeric order is lexicographic order).
+ * Results are ascending and free of repeats: the result is a set.
+ *
+ * Domain. 1 <= n; 1 <= l <= 32; l <= m; 0 <= d < l. Input bytes must be
+ * uppercase 'A','C','G','T'; anything else is PMS_EBASE, and
+ * pms_last_error() names the string and offset of the first bad byte.
+ *
+ * Ownership. Inputs are copied before a call returns (pms_submit included),
+ * so the caller may free them at once. Result arrays belong to the context
+ * and stay valid until the next call on that context that returns results
+ * (pms_solve / pms_solve_batch) or until pms_release / pms_destroy.
+ *
+ * Threads. A context is not thread-safe: use one per host thread. The
+ * serving entry points (pms_submit / pms_poll / pms_release) may be called
+ * while the context's own engine thread runs requests on the device.
+ *
+ * Errors. Every int-returning call returns PMS_OK (0), PMS_PENDING (1,
+ * pms_poll only) or a negative PMS_E* status; pms_last_error() gives a
+ * human-readable detail of the last failure on that context.
+ */
+#ifndef PMS_H
+#define PMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PMS_OK = 0,
+    PMS_PENDING = 1,      /* pms_poll: request admitted or queued, not done */
+    PMS_EINVAL = -1,      /* bad sizes, parameters, ticket or NULL pointer */
+    PMS_EBASE = -2,       /* an input byte is not one of A, C, G, T */
+    PMS_ENOMEM = -3,      /* device memory budget or capacity too small */
+    PMS_EDEVICE = -4,     /* HIP runtime error */
+    PMS_EBUSY = -5        /* serving queue full */
+};
+
+/* Which device algorithm computes the set. All give identical results. */
+enum {
+    PMS_PATH_AUTO = 0,    /* cost model picks the cheapest of 1 and 3 */
+    PMS_PATH_FILTER = 1,  /* sample-driven: d-neighbourhoods of the l-mers of
+                             s_1 (Observation 3.1 with q = n) filtered by
+                             XOR/popcount Hamming tests against s_2..s_n */
+    PMS_PATH_BITSET = 2,  /* pattern-driven, memory-heavy: one bit per l-mer
+                             of the 4^l space resident in device memory,
+                             one pass per string ANDs in the union of the
+                             d-spheres of its l-mers (needs 4^l/8 bytes) */
+    PMS_PATH_TILED = 3    /* pattern-driven, tiled: the 4^l space split into
+                             tiles held on chip; each tile ANDs the strings'
+                             sphere unions until few codes are left, then
+                             filters those by Hamming tests */
+};
+
+typedef struct pms_ctx pms_ctx;
+
+typedef struct {
+    int device;               /* HIP device ordinal */
+    int path;                 /* PMS_PATH_*; 0 = auto */
+    size_t mem_budget_bytes;  /* device memory the context may hold for
+                                 per-call buffers; 0 = 90% of free memory */
+    const char *tune_cache;   /* autotuner cache file (read at create,
+                                 written after tuning); NULL = in memory */
+    int serve_slots;          /* serving: max requests on the device at
+                                 once; 0 = 64 */
+    int serve_queue;          /* serving: max requests waiting for
+                                 admission; 0 = 4096 */
+} pms_options;
+
+/* Fill *opt with the defaults above (device 0, auto path). */
+void pms_default_options(pms_options *opt);
+
+/* Create a context on opt->device (opt may be NULL for the defaults).
+ * *out receives the context, or NULL on failure (status returned). */
+int pms_create(pms_ctx **out, const pms_options *opt);
+
+/* Stop the serving engine, free every device and host buffer. NULL-safe. */
+void pms_destroy(pms_ctx *ctx);
+
+/* Detail of the last failure on ctx ("" if none); valid until the next call
+ * on ctx. With ctx == NULL: the last pms_create failure of this thread. */
+const char *pms_last_error(const pms_ctx *ctx);
+
+/* Static name of a status code. */
+const char *pms_status_string(int status);
+
+/*
+ * Solve one instance. seqs: n*m bytes, row-major (string i at seqs+i*m),
+ * host memory. On PMS_OK *motifs points at *count ascending codes owned by
+ * ctx (NULL when *count == 0).
+ */
+int pms_solve(pms_ctx *ctx, const char *seqs, int n, int m, int l, int d,
+              const uint64_t **motifs, size_t *count);
+
+/*
+ * Solve one instance whose input already sits in device memory.
+ * d_seqs: n*m ASCII bytes in device memory. stream: a hipStream_t to run
+ * on (NULL = the context's own stream). d_out: device array of cap codes.
+ * On PMS_OK the stream has been synchronised, *count holds the number of
+ * motifs and d_out[0..*count) the ascending codes. If cap < *count the
+ * call returns PMS_ENOMEM with *count set to the size needed and d_out
+ * unspecified. The input buffer is only read.
+ */
+int pms_solve_device(pms_ctx *ctx, const uint8_t *d_seqs, int n, int m,
+                     int l, int d, void *stream, uint64_t *d_out, size_t cap,
+                     size_t *count);
+
+/* One instance of a batch or a serving request. seqs: n*m host bytes. */
+typedef struct {
+    const char *seqs;
+    int n, m, l, d;
+} pms_instance;
+
+/* Result of one instance. motifs: ctx-owned, ascending; status: PMS_*. */
+typedef struct {
+    const uint64_t *motifs;
+    size_t count;
+    int status;
+} pms_result;
+
+/*
+ * Solve k independent instances of any sizes together: all of them run in
+ * one persistent launch that drains a device work queue, replayed as a
+ * captured HIP graph when the same batch shape repeats. out[i] receives
+ * instance i's result (status PMS_EBASE / PMS_EINVAL for a bad instance;
+ * the others still complete). Returns PMS_OK if every instance succeeded,
+ * else the first failing status.
+ */
+int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
+                    pms_result *out);
+
+/*
+ * Serving (continuous batching). pms_submit copies the request and queues
+ * it; the context's engine thread admits queued requests while device
+ * memory and slots allow and runs admitted requests' work together, a
+ * bounded slice per launch, so requests join and leave between launches.
+ * *ticket identifies the request. PMS_EBUSY if the waiting queue is full;
+ * PMS_EINVAL for a bad shape, for a shape the tiled path does not suit
+ * (l < 3, or more than 4^13 tiles; use pms_solve) and PMS_ENOMEM for a
+ * request larger than the serving pool (all checked before queueing).
+ * Bad bytes are found on the device: the result's status is PMS_EBASE.
+ * While requests are in flight, do not call pms_solve* or pms_autotune on
+ * the same context from another thread.
+ */
+int pms_submit(pms_ctx *ctx, const pms_instance *in, uint64_t *ticket);
+
+/* PMS_PENDING until the request finished; then PMS_OK (or its error) with
+ * *out filled; the result stays valid until pms_release(ticket). */
+int pms_poll(pms_ctx *ctx, uint64_t ticket, pms_result *out);
+
+/* Block until the request finished (or timeout_ms elapsed: PMS_PENDING). */
+int pms_wait(pms_ctx *ctx, uint64_t ticket, int timeout_ms, pms_result *out);
+
+/* Forget a finished request and free its result. */
+int pms_release(pms_ctx *ctx, uint64_t ticket);
+
+/* Times of a request on the library's steady clock (pms_clock_ms):
+ * submission, admission to the device and completion (0 if not yet). */
+int pms_ticket_times(pms_ctx *ctx, uint64_t ticket, double *t_submit_ms,
+                     double *t_admit_ms, double *t_done_ms);
+
+/* Milliseconds on the steady clock used by pms_ticket_times. */
+double pms_clock_ms(void);
+
+/* Timing and work counters of the last pms_solve / pms_solve_device /
+ * pms_solve_batch call. Kernel times come from HIP events recorded on the
+ * stream each kernel ran on. */
+typedef struct {
+    int path;                 /* PMS_PATH_* actually used */
+    int tile_suffix;          /* tiled/bitset: bases per tile suffix (s) */
+    double ms_total;          /* host wall time of the call */
+    double ms_index;          /* pack + l-mer index kernels */
+    double ms_main;           /* filter / tiled / bitset kernels */
+    double ms_output;         /* compaction, ordering, copies */
+    uint64_t main_launches;   /* launches of the main kernel */
+    uint64_t hcanon;          /* filter path: Hamming tests in the
+                                 canonical order of the sample-driven
+                                 method; 0 for other paths */
+    uint64_t tiles;           /* tiled/bitset: tiles processed */
+    uint64_t tile_passes;     /* tiled/bitset: (tile, string) passes run */
+    uint64_t marks;           /* tiled/bitset: 64-bit sphere-word ORs */
+    uint64_t filter_tests;    /* tiled: Hamming tests of the filter stage */
+    uint64_t bytes_main;      /* bitset path: device bytes read+written */
+    uint64_t retries;         /* output-capacity retries */
+} pms_stats;
+
+int pms_last_stats(const pms_ctx *ctx, pms_stats *out);
+
+/* Serving statistics since pms_create. */
+typedef struct {
+    uint64_t submitted, completed, launches;
+    uint64_t max_inflight;
+    double busy_ms;           /* engine time with work on the device */
+} pms_serve_stats;
+
+int pms_serve_stats_get(const pms_ctx *ctx, pms_serve_stats *out);
+
+/*
+ * Filter path only: copy the per-reference Hamming-test counts of the last
+ * filter-path solve (entry j: the tests spent on candidates from the l-mer
+ * of s_1 at offset j). n_refs must be m-l+1 of that solve.
+ */
+int pms_last_hcanon_per_ref(const pms_ctx *ctx, uint64_t *out, size_t n_refs);
+
+/*
+ * Autotuner. Times every tile configuration (suffix length, survivor
+ * threshold) of the tiled kernel on a synthetic instance shaped like
+ * (n, m, l, d), keeps the fastest, and stores it in the context's tuning
+ * table (and tune_cache file, if set) under the key (l, d, n-bucket,
+ * m-bucket). Every configuration gives the same motif set; only speed
+ * differs. *best_s / *best_t receive the choice (may be NULL).
+ */
+int pms_autotune(pms_ctx *ctx, int n, int m, int l, int d, int *best_s,
+                 int *best_t);
+
+/* Override the tile configuration used for (l, d) from now on (0 = back to
+ * the tuned or default choice). For testing configuration invariance. */
+int pms_set_tile_config(pms_ctx *ctx, int l, int d, int s, int surv_t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMS_H */

@@ -1,0 +1,324 @@
+// k_filter.hip -- sample-driven path: d-neighbourhood candidates of the
+// l-mers of s_1, filtered by XOR/popcount Hamming tests against s_2..s_n.
+//
+// Observation 3.1 with q = n: every motif lies in B(x, d) for some l-mer x
+// of s_1, so the candidates are x XOR mu for every l-mer x of s_1 and every
+// mu in Mask(l, d), the set of digit-wise XOR masks with at most d nonzero
+// 2-bit digits (XOR of a base code with 1, 2 or 3 gives each of the three
+// other bases, so x XOR Mask(l,d) is B(x,d), each element once; |Mask| =
+// n_B(l,d) of Table 3.1).
+//
+// The filter is PMS8's "find motifs for some strings, then test them
+// against the rest" (Sec. 3.2.4) with the Hamming test of Sec. 3.3.1 on bit
+// planes: d_H = popcount((hi_a ^ hi_b) | (lo_a ^ lo_b)). A candidate is
+// tested against s_2, s_3, ... in input order and dropped at the first
+// string with no l-mer within distance d. Between strings the survivors of
+// a workgroup are compacted so that every lane keeps testing live
+// candidates.
+//
+// Each motif can be reached from several x. It is kept only from the first
+// (lowest offset) l-mer x of s_1 within distance d of it, so the survivors
+// are already free of repeats; they are sorted afterwards.
+#include "pms_internal.h"
+
+namespace pms {
+
+constexpr int kFPer = 8;                    // candidates per thread
+constexpr int kFBlock = kTPB * kFPer;       // candidates per block step
+
+__device__ __forceinline__ uint64_t binom(int n, int k)
+{
+    if (k < 0 || k > n)
+        return 0;
+    uint64_t c = 1;
+    for (int i = 0; i < k; i++)
+        c = c * (uint64_t)(n - i) / (uint64_t)(i + 1);
+    return c;
+}
+
+// Entry e of Mask(l, d) in bit-plane form. Entries are ordered by weight k,
+// then by the rank of the position set (lexicographic), then by the base-3
+// digits that pick the XOR value 1..3 at each chosen position.
+__global__ void k_masks(int l, int d, uint2 *masks, uint64_t nb)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nb)
+        return;
+    uint64_t r = e;
+    int k = 0;
+    uint64_t p3 = 1;
+    for (;;) {
+        const uint64_t cnt = binom(l, k) * p3;
+        if (r < cnt || k == d)
+            break;
+        r -= cnt;
+        k++;
+        p3 *= 3;
+    }
+    uint64_t comb = r / p3;
+    uint64_t digs = r - comb * p3;
+    uint32_t hi = 0, lo = 0;
+    int left = k;
+    for (int v = 0; v < l && left > 0; v++) {
+        const uint64_t c = binom(l - 1 - v, left - 1);
+        if (comb < c) {
+            const uint32_t delta = 1u + (uint32_t)(digs % 3);
+            digs /= 3;
+            hi |= (delta >> 1) << v;
+            lo |= (delta & 1u) << v;
+            left--;
+        } else {
+            comb -= c;
+        }
+    }
+    masks[e] = make_uint2(hi, lo);
+}
+
+hipError_t launch_masks(int l, int d, uint2 *masks, uint64_t nb,
+                        hipStream_t st)
+{
+    const uint64_t blocks = (nb + 255) / 256;
+    hipLaunchKernelGGL(k_masks, dim3((unsigned)blocks), dim3(256), 0, st, l,
+                       d, masks, nb);
+    return hipGetLastError();
+}
+
+struct FilterShared {
+    uint2 cand[kFBlock];       // live candidates (bit planes)
+    uint32_t ref[kFBlock];     // offset of the generating l-mer of s_1
+    uint32_t hc[kFBlock + 2];  // canonical tests per reference in the block
+    unsigned int red[kWaves];
+    unsigned long long blk;
+    unsigned long long off;
+};
+
+__device__ __forceinline__ unsigned int blk_exscan(unsigned int v,
+                                                   unsigned int *red,
+                                                   unsigned int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned int y = __shfl_up(x, o, 64);
+        if (lane >= o)
+            x += y;
+    }
+    __syncthreads();
+    if (lane == 63)
+        red[wid] = x;
+    __syncthreads();
+    unsigned int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+        if (w < wid)
+            before += red[w];
+        tot += red[w];
+    }
+    *total = tot;
+    return before + x - v;
+}
+
+// Minimum distance from each of the thread's candidates to the l-mers of
+// one string; the l-mer is the same for the whole wave (scalar loads).
+template <int K>
+__device__ __forceinline__ void scan_string(const uint2 *yp, int L,
+                                            const uint2 (&c)[K],
+                                            uint32_t (&mind)[K], int d,
+                                            unsigned int live_mask)
+{
+    int j = 0;
+    for (; j + 16 <= L; j += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; u += 2) {
+            const uint2 y0 = yp[j + u], y1 = yp[j + u + 1];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const uint32_t h0 = __popc((c[k].x ^ y0.x) | (c[k].y ^ y0.y));
+                const uint32_t h1 = __popc((c[k].x ^ y1.x) | (c[k].y ^ y1.y));
+                mind[k] = min(mind[k], min(h0, h1));
+            }
+        }
+        bool done = true;
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            done = done && (!((live_mask >> k) & 1u) || mind[k] <= (uint32_t)d);
+        if (__all(done))
+            return;
+    }
+    for (; j < L; j++) {
+        const uint2 y = yp[j];
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            mind[k] = min(mind[k],
+                          (uint32_t)__popc((c[k].x ^ y.x) | (c[k].y ^ y.y)));
+    }
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
+         unsigned long long *next_block, uint64_t *heap,
+         unsigned long long *heap_top, unsigned long long heap_cap,
+         unsigned long long *hc_per_ref)
+{
+    __shared__ FilterShared sh;
+    const InstDev I = *inst;
+    const int tid = threadIdx.x;
+    const int L = I.L, d = I.d, l = I.l;
+    const uint2 *x_planes = I.planes;                // row 0 = s_1
+    const uint64_t total = (uint64_t)L * nb;
+    const uint64_t nblocks = (total + kFBlock - 1) / kFBlock;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0)
+            sh.blk = atomicAdd(next_block, 1ull);
+        __syncthreads();
+        const uint64_t b = sh.blk;
+        if (b >= nblocks)
+            break;
+        const uint64_t f0 = b * kFBlock;
+        const uint32_t x_first = (uint32_t)(f0 / nb);
+        for (int i = tid; i < kFBlock + 2; i += kTPB)
+            sh.hc[i] = 0;
+
+        // stage 0: build this thread's candidates
+        uint2 c[kFPer];
+        uint32_t ref[kFPer];
+        unsigned int live = 0;
+#pragma unroll
+        for (int k = 0; k < kFPer; k++) {
+            const uint64_t f = f0 + (uint64_t)k * kTPB + tid;
+            c[k] = make_uint2(0, 0);
+            ref[k] = 0;
+            if (f < total) {
+                const uint32_t x = (uint32_t)(f / nb);
+                const uint64_t e = f - (uint64_t)x * nb;
+                const uint2 xp = x_planes[x];
+                const uint2 mu = masks[e];
+                c[k] = make_uint2(xp.x ^ mu.x, xp.y ^ mu.y);
+                ref[k] = x;
+                live |= 1u << k;
+            }
+        }
+        __syncthreads();   // hc cleared
+
+        int nlive = kFBlock;   // upper bound; slots carry live bits
+        for (int si = 1; si < I.n && nlive > 0; si++) {
+            const uint2 *yp = I.planes + (size_t)si * L;
+            uint32_t mind[kFPer];
+#pragma unroll
+            for (int k = 0; k < kFPer; k++) {
+                mind[k] = 255;
+                if ((live >> k) & 1u)
+                    atomicAdd(&sh.hc[ref[k] - x_first], (uint32_t)L);
+            }
+            if (__any(live != 0))
+                scan_string<kFPer>(yp, L, c, mind, d, live);
+            unsigned int keep = 0, nk = 0;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++)
+                if (((live >> k) & 1u) && mind[k] <= (uint32_t)d) {
+                    keep |= 1u << k;
+                    nk++;
+                }
+            // compact the survivors of the block and deal them out again
+            unsigned int tot;
+            const unsigned int pos = blk_exscan(nk, sh.red, &tot);
+            unsigned int w = pos;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++)
+                if ((keep >> k) & 1u) {
+                    sh.cand[w] = c[k];
+                    sh.ref[w] = ref[k];
+                    w++;
+                }
+            __syncthreads();
+            nlive = (int)tot;
+            live = 0;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++) {
+                const int i = k * kTPB + tid;
+                if (i < nlive) {
+                    c[k] = sh.cand[i];
+                    ref[k] = sh.ref[i];
+                    live |= 1u << k;
+                }
+            }
+            __syncthreads();
+        }
+
+        // survivors of every string: keep each motif from its first x only
+        unsigned int keep = 0, nk = 0;
+#pragma unroll
+        for (int k = 0; k < kFPer; k++) {
+            if (!((live >> k) & 1u))
+                continue;
+            bool first = true;
+            for (uint32_t xj = 0; xj < ref[k] && first; xj++) {
+                const uint2 y = x_planes[xj];
+                first = __popc((c[k].x ^ y.x) | (c[k].y ^ y.y)) > d;
+            }
+            if (first) {
+                keep |= 1u << k;
+                nk++;
+            }
+        }
+        unsigned int tot;
+        const unsigned int pos = blk_exscan(nk, sh.red, &tot);
+        if (tid == 0 && tot)
+            sh.off = atomicAdd(heap_top, (unsigned long long)tot);
+        __syncthreads();
+        if (tot) {
+            const unsigned long long off = sh.off;
+            unsigned int w = pos;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++)
+                if ((keep >> k) & 1u) {
+                    if (off + w < heap_cap) {
+                        // planes -> code, first base in the top digit
+                        uint64_t code = 0;
+                        for (int p = 0; p < l; p++)
+                            code = (code << 2) |
+                                   ((((c[k].x >> p) & 1u) << 1) |
+                                    ((c[k].y >> p) & 1u));
+                        heap[off + w] = code;
+                    }
+                    w++;
+                }
+        }
+        // flush the per-reference test counts of this block
+        if (hc_per_ref) {
+            const uint64_t f1 = min(f0 + kFBlock, total);
+            const uint32_t x_last = (uint32_t)((f1 - 1) / nb);
+            for (uint32_t x = x_first + tid; x <= x_last; x += kTPB)
+                if (sh.hc[x - x_first])
+                    atomicAdd(&hc_per_ref[x],
+                              (unsigned long long)sh.hc[x - x_first]);
+        }
+    }
+}
+
+hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
+                         uint64_t nb, unsigned long long *next_block,
+                         uint64_t *heap, unsigned long long *heap_top,
+                         unsigned long long heap_cap,
+                         unsigned long long *hc_per_ref, int grid,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(kTPB), 0, st, d_inst, masks,
+                       nb, next_block, heap, heap_top, heap_cap, hc_per_ref);
+    return hipGetLastError();
+}
+
+int filter_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filter, kTPB, 0) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+}  // namespace pms

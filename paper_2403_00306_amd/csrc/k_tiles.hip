@@ -1,0 +1,549 @@
+// k_tiles.hip -- pattern-driven kernels over the 4^l code space.
+//
+// The pattern-driven view (Sec. 1.3.1) asks, for every l-mer M, whether each
+// string s_i has an l-mer y with d_H(M, y) <= d, i.e. whether M lies in
+// U_i = union over y in s_i of the sphere B(y, d) (Table 3.1). The motif set
+// is the intersection of U_1..U_n. These kernels hold U_i and the running
+// intersection as bitsets over the code space, one bit per l-mer code
+// (first base in the top digit, so bit order is code order).
+//
+// Tiling. A tile fixes the first l-s bases (the prefix P) and covers all
+// 4^s suffixes: 4^(s-3) 64-bit words in LDS, word index = suffix bases
+// 0..s-4, bit index = the last 3 bases. An l-mer y reaches the tile iff
+// k = d_H(prefix(y), P) <= d, and then marks exactly the suffixes within
+// distance r = d - k of suffix(y). Marking goes by words: for every XOR
+// mask over the word-index digits with weight w <= r, the word
+// (index(y) ^ mask) receives the precomputed mask of 3-base codes within
+// distance min(r - w, 3) of y's last 3 bases.
+//
+// Tiled path (PMS_PATH_TILED): a workgroup keeps one tile's intersection in
+// registers and ANDs the strings in one by one; the tile stops when it is
+// empty, and when at most surv_t codes are left it tests those codes
+// directly against the remaining strings (the XOR/popcount Hamming filter
+// of Sec. 3.3.1 with early exit at the first string without a hit).
+//
+// Bitset path (PMS_PATH_BITSET, memory heavy): the whole 4^l-bit
+// intersection lives in device memory and each string is one pass over
+// every live tile: read 4^s bits, AND the string's union, write back.
+#include "pms_internal.h"
+
+namespace pms {
+
+struct TileShared {
+    unsigned long long U[kMaxWords];   // the string's union on this tile
+    unsigned long long m3[256];        // word masks, copy of Tables::m3
+    union {
+        uint32_t ylist[kYChunk];       // suffix codes of reaching l-mers
+        uint64_t surv[kSurvMax];       // filter stage: codes left
+    };
+    int rcnt[kMaxL + 1];               // reaching l-mers per radius r
+    int roff[kMaxL + 2];
+    int rpos[kMaxL + 1];
+    unsigned long long red64[kWaves];
+    unsigned int red32[kWaves];
+    unsigned long long bcast;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup; every thread gets the total.
+__device__ __forceinline__ unsigned long long
+block_sum64(unsigned long long v, unsigned long long *red)
+{
+    v = wave_sum64(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++)
+        t += red[w];
+    return t;
+}
+
+// Exclusive prefix sum over the workgroup in thread order.
+__device__ __forceinline__ unsigned int
+block_exscan(unsigned int v, unsigned int *red, unsigned int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned int y = __shfl_up(x, o, 64);
+        if (lane >= o)
+            x += y;
+    }
+    __syncthreads();
+    if (lane == 63)
+        red[wid] = x;
+    __syncthreads();
+    unsigned int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+        if (w < wid)
+            before += red[w];
+        tot += red[w];
+    }
+    *total = tot;
+    return before + x - v;
+}
+
+// Bit planes of a tile prefix (pl bases, first base in the top digit).
+__device__ __forceinline__ void prefix_planes(uint64_t P, int pl,
+                                              uint32_t &hi, uint32_t &lo)
+{
+    hi = 0;
+    lo = 0;
+    for (int p = 0; p < pl; p++) {
+        const uint32_t dig = (uint32_t)(P >> (2 * (pl - 1 - p))) & 3u;
+        hi |= (dig >> 1) << p;
+        lo |= (dig & 1u) << p;
+    }
+}
+
+// OR into sh.U the union of the d-spheres of string `seq`'s l-mers,
+// restricted to the tile with prefix planes (Phi, Plo). Ends with a barrier.
+// Returns (in thread 0) the number of word ORs done.
+__device__ unsigned long long mark_string(const InstDev &I, int seq,
+                                          uint32_t Phi, uint32_t Plo,
+                                          uint32_t premask, TileShared &sh,
+                                          const Tables &tb)
+{
+    const int tid = threadIdx.x;
+    const int d = I.d, s = I.s, q = s - 3;
+    const uint2 *yp = I.planes + (size_t)seq * I.L;
+    const uint64_t *yc = I.codes + (size_t)seq * I.L;
+    const uint32_t sufmask = (1u << (2 * s)) - 1u;
+    const uint16_t *ball = tb.ball + tb.ball_base[q];
+    const int *boff = tb.ball_off + q * 8;
+    unsigned long long marks = 0;
+    for (int y0 = 0; y0 < I.L; y0 += kYChunk) {
+        const int ny = min(kYChunk, I.L - y0);
+        if (tid <= d)
+            sh.rcnt[tid] = 0;
+        __syncthreads();
+        for (int j = tid; j < ny; j += kTPB) {
+            const uint2 y = yp[y0 + j];
+            const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
+            if (k <= d)
+                atomicAdd(&sh.rcnt[d - k], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int r = 0; r <= d; r++) {
+                sh.roff[r] = acc;
+                sh.rpos[r] = acc;
+                acc += sh.rcnt[r];
+            }
+            sh.roff[d + 1] = acc;
+        }
+        __syncthreads();
+        for (int j = tid; j < ny; j += kTPB) {
+            const uint2 y = yp[y0 + j];
+            const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
+            if (k <= d) {
+                const int p = atomicAdd(&sh.rpos[d - k], 1);
+                sh.ylist[p] = (uint32_t)yc[y0 + j] & sufmask;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r <= d; r++) {
+            const int c = sh.rcnt[r];
+            if (c == 0)
+                continue;
+            const int rw = min(r, q);
+            const uint32_t bs = (uint32_t)boff[rw + 1];
+            const uint32_t total = (uint32_t)c * bs;
+            const uint64_t magic = (0x100000000ull + bs - 1) / bs;
+            const uint32_t *yl = sh.ylist + sh.roff[r];
+            marks += total;
+            for (uint32_t f = tid; f < total; f += kTPB) {
+                uint32_t yi = (uint32_t)(((uint64_t)f * magic) >> 32);
+                int e = (int)(f - yi * bs);
+                if (e < 0) {
+                    yi--;
+                    e += (int)bs;
+                }
+                const uint32_t ys = yl[yi];
+                const uint32_t ent = ball[e];
+                const int tt = min(r - (int)(ent >> 12), 3);
+                const uint32_t widx = (ys >> 6) ^ (ent & 0xfffu);
+                atomicOr(&sh.U[widx], sh.m3[(ys & 63u) * 4u + (uint32_t)tt]);
+            }
+        }
+        __syncthreads();
+    }
+    return marks;
+}
+
+// Write the set bits of the tile (words in sh.U) as ascending codes to
+// dst[0..). Thread t owns a contiguous block of words so that thread order
+// is code order. Codes: (tile << 2s) | (word << 6) | bit.
+__device__ void emit_words(const TileShared &sh, int W, uint64_t tile, int s,
+                           uint64_t *dst, bool write, unsigned int *red)
+{
+    const int tid = threadIdx.x;
+    const int per = (W + kTPB - 1) / kTPB;
+    const int w0 = tid * per;
+    const int w1 = min(w0 + per, W);
+    unsigned int cnt = 0;
+    for (int w = w0; w < w1; w++)
+        cnt += __popcll(sh.U[w]);
+    unsigned int tot;
+    unsigned int pos = block_exscan(cnt, red, &tot);
+    if (!write)
+        return;
+    const uint64_t base = tile << (2 * s);
+    for (int w = w0; w < w1; w++) {
+        unsigned long long v = sh.U[w];
+        while (v) {
+            const int b = __ffsll(v) - 1;
+            v &= v - 1;
+            dst[pos++] = base | ((uint64_t)w << 6) | (uint64_t)b;
+        }
+    }
+}
+
+// Convert a code (first base in the top digit) to bit planes.
+__device__ __forceinline__ uint2 code_planes(uint64_t c, int l)
+{
+    uint32_t hi = 0, lo = 0;
+    for (int p = 0; p < l; p++) {
+        const uint32_t dig = (uint32_t)(c >> (2 * (l - 1 - p))) & 3u;
+        hi |= (dig >> 1) << p;
+        lo |= (dig & 1u) << p;
+    }
+    return make_uint2(hi, lo);
+}
+
+struct StatAcc {
+    unsigned long long passes, marks, ftests, tiles;
+};
+
+// One tile of the tiled path.
+__device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
+                         const Tables &tb, StatAcc &acc)
+{
+    uint32_t *tile_cnt = I.tile_cnt;
+    uint64_t *tile_heap_off = I.tile_heap_off;
+    uint64_t *heap = I.heap;
+    unsigned long long *heap_top = I.heap_top;
+    const unsigned long long heap_cap = I.heap_cap;
+    const int tid = threadIdx.x;
+    const int s = I.s, q = s - 3, pl = I.l - s;
+    const int W = 1 << (2 * q);
+    const uint64_t g = t;
+    uint32_t Phi, Plo;
+    prefix_planes(t, pl, Phi, Plo);
+    const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
+    __syncthreads();   // the previous tile may still be reading sh.U
+
+    unsigned long long A[kWordsPerThread];
+    unsigned long long total = 0;
+    int si = 0;
+    bool to_filter = false;
+    for (si = 0; si < I.n; si++) {
+        const int seq = I.order[si];
+        for (int w = tid; w < W; w += kTPB)
+            sh.U[w] = 0;
+        __syncthreads();
+        const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
+                                                  sh, tb);
+        unsigned long long cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; k++) {
+            const int w = tid + k * kTPB;
+            if (w < W) {
+                const unsigned long long u = sh.U[w];
+                A[k] = (si == 0) ? u : (A[k] & u);
+                cnt += __popcll(A[k]);
+            }
+        }
+        total = block_sum64(cnt, sh.red64);
+        if (tid == 0) {
+            acc.passes++;
+            acc.marks += mk;
+        }
+        if (total == 0)
+            break;
+        if (total <= (unsigned long long)I.surv_t && si + 1 < I.n) {
+            to_filter = true;
+            break;
+        }
+    }
+    if (tid == 0)
+        acc.tiles++;
+    if (total == 0) {
+        if (tid == 0) {
+            tile_cnt[g] = 0;
+            tile_heap_off[g] = 0;
+        }
+        return;
+    }
+    // the intersection back to LDS, in word order
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; k++) {
+        const int w = tid + k * kTPB;
+        if (w < W)
+            sh.U[w] = A[k];
+    }
+    __syncthreads();
+
+    if (!to_filter) {
+        // every string ANDed in: all remaining codes are motifs
+        if (tid == 0) {
+            const unsigned long long off = atomicAdd(heap_top, total);
+            sh.bcast = off;
+            tile_cnt[g] = (uint32_t)total;
+            tile_heap_off[g] = off;
+        }
+        __syncthreads();
+        const unsigned long long off = sh.bcast;
+        const bool fits = off + total <= heap_cap;
+        emit_words(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
+        return;
+    }
+
+    // ---- filter stage: test the few codes left against the rest --------
+    emit_words(sh, W, t, s, sh.surv, true, sh.red32);
+    __syncthreads();
+    const int nsurv = (int)total;
+    const bool have = tid < nsurv;
+    uint2 cp = make_uint2(0, 0);
+    if (have)
+        cp = code_planes(sh.surv[tid], I.l);
+    bool alive = have;
+    const bool wave_has = __ballot(have) != 0;
+    for (int sj = si + 1; sj < I.n; sj++) {
+        const int nalive = __syncthreads_count(alive);
+        if (nalive == 0)
+            break;
+        if (tid == 0)
+            acc.ftests += (unsigned long long)nalive * (unsigned long long)I.L;
+        if (wave_has && __ballot(alive) != 0) {
+            const uint2 *yp = I.planes + (size_t)I.order[sj] * I.L;
+            uint32_t mind = 255;
+            int j = 0;
+            for (; j + 8 <= I.L; j += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    const uint2 y0 = yp[j + u], y1 = yp[j + u + 1];
+                    const uint32_t h0 = __popc((cp.x ^ y0.x) | (cp.y ^ y0.y));
+                    const uint32_t h1 = __popc((cp.x ^ y1.x) | (cp.y ^ y1.y));
+                    mind = min(mind, min(h0, h1));
+                }
+                if (__all(!alive || mind <= (uint32_t)I.d))
+                    break;
+            }
+            if (j + 8 > I.L) {
+                for (; j < I.L; j++) {
+                    const uint2 y = yp[j];
+                    mind = min(mind, (uint32_t)__popc((cp.x ^ y.x) |
+                                                      (cp.y ^ y.y)));
+                }
+            }
+            alive = alive && mind <= (uint32_t)I.d;
+        }
+    }
+    // ordered compaction of the survivors into the heap
+    unsigned int ntot;
+    const unsigned int pos = block_exscan(alive ? 1u : 0u, sh.red32, &ntot);
+    if (tid == 0) {
+        unsigned long long off = 0;
+        if (ntot)
+            off = atomicAdd(heap_top, (unsigned long long)ntot);
+        sh.bcast = off;
+        tile_cnt[g] = ntot;
+        tile_heap_off[g] = off;
+    }
+    __syncthreads();
+    const unsigned long long off = sh.bcast;
+    if (alive && off + ntot <= heap_cap)
+        heap[off + pos] = sh.surv[tid];
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
+        uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
+{
+    __shared__ TileShared sh;
+    __shared__ int s_item;
+    for (int i = threadIdx.x; i < 256; i += kTPB)
+        sh.m3[i] = tb.m3[i];
+    StatAcc acc = {0, 0, 0, 0};
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= nitems)
+            break;
+        WorkItem w;
+        if (items) {
+            w = items[it];
+        } else {
+            // implicit list: instance 0 split into chunks of `chunk` tiles
+            w.inst = 0;
+            w.t0 = (uint64_t)it * chunk;
+            w.t1 = min(w.t0 + chunk, insts[0].ntiles);
+        }
+        const InstDev I = insts[w.inst];
+        for (uint64_t t = w.t0; t < w.t1; t++)
+            run_tile(I, t, sh, tb, acc);
+    }
+    if (threadIdx.x == 0 && stats) {
+        atomicAdd(&stats->passes, acc.passes);
+        atomicAdd(&stats->marks, acc.marks);
+        atomicAdd(&stats->ftests, acc.ftests);
+        atomicAdd(&stats->tiles, acc.tiles);
+    }
+}
+
+hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
+                        int nitems, uint64_t chunk, unsigned int *d_next,
+                        Tables tb, TileStats *stats, int grid, hipStream_t st)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_tiled, dim3(grid), dim3(kTPB), 0, st, d_insts,
+                       d_items, nitems, chunk, d_next, tb, stats);
+    return hipGetLastError();
+}
+
+int tiled_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled, kTPB, 0) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+// ---- memory-heavy bitset path ---------------------------------------------
+
+__global__ __launch_bounds__(kTPB) void
+k_bitset_pass(const InstDev *inst, int pass, Tables tb,
+              unsigned long long *A, uint8_t *alive, TileStats *stats)
+{
+    __shared__ TileShared sh;
+    const InstDev I = *inst;
+    const int tid = threadIdx.x;
+    const int s = I.s, q = s - 3, pl = I.l - s;
+    const int W = 1 << (2 * q);
+    const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
+    const int seq = I.order[pass];
+    for (int i = tid; i < 256; i += kTPB)
+        sh.m3[i] = tb.m3[i];
+    unsigned long long marks = 0, passes = 0;
+    for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
+        if (pass > 0 && !alive[t])
+            continue;
+        for (int w = tid; w < W; w += kTPB)
+            sh.U[w] = 0;
+        __syncthreads();
+        uint32_t Phi, Plo;
+        prefix_planes(t, pl, Phi, Plo);
+        marks += mark_string(I, seq, Phi, Plo, premask, sh, tb);
+        passes++;
+        unsigned long long *Ag = A + t * (uint64_t)W;
+        int nz = 0;
+        for (int w = tid; w < W; w += kTPB) {
+            const unsigned long long u = sh.U[w];
+            const unsigned long long a = pass ? (Ag[w] & u) : u;
+            Ag[w] = a;
+            nz |= (a != 0);
+        }
+        const int any = __syncthreads_or(nz);
+        if (tid == 0)
+            alive[t] = (uint8_t)(any != 0);
+    }
+    if (tid == 0 && stats) {
+        atomicAdd(&stats->passes, passes);
+        atomicAdd(&stats->marks, marks);
+    }
+}
+
+hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
+                              unsigned long long *A, uint8_t *alive,
+                              TileStats *stats, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                       pass, tb, A, alive, stats);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_bitset_count(const InstDev *inst, const unsigned long long *A,
+               const uint8_t *alive, uint32_t *tile_cnt)
+{
+    __shared__ unsigned long long red[kWaves];
+    const InstDev I = *inst;
+    const int W = 1 << (2 * (I.s - 3));
+    for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
+        unsigned long long c = 0;
+        if (alive[t]) {
+            const unsigned long long *Ag = A + t * (uint64_t)W;
+            for (int w = threadIdx.x; w < W; w += kTPB)
+                c += __popcll(Ag[w]);
+        }
+        c = block_sum64(c, red);
+        if (threadIdx.x == 0)
+            tile_cnt[t] = (uint32_t)c;
+    }
+}
+
+hipError_t launch_bitset_count(const InstDev *d_inst,
+                               const unsigned long long *A,
+                               const uint8_t *alive, uint32_t *tile_cnt,
+                               int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bitset_count, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                       A, alive, tile_cnt);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_bitset_emit(const InstDev *inst, const unsigned long long *A,
+              const uint32_t *tile_cnt, const uint64_t *tile_pos,
+              uint64_t *out, unsigned long long cap)
+{
+    __shared__ TileShared sh;
+    const InstDev I = *inst;
+    const int W = 1 << (2 * (I.s - 3));
+    for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
+        if (tile_cnt[t] == 0)
+            continue;
+        const unsigned long long *Ag = A + t * (uint64_t)W;
+        for (int w = threadIdx.x; w < W; w += kTPB)
+            sh.U[w] = Ag[w];
+        __syncthreads();
+        const uint64_t pos = tile_pos[t];
+        const bool fits = pos + tile_cnt[t] <= cap;
+        emit_words(sh, W, t, I.s, out + (fits ? pos : 0), fits, sh.red32);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_bitset_emit(const InstDev *d_inst,
+                              const unsigned long long *A,
+                              const uint32_t *tile_cnt,
+                              const uint64_t *tile_pos, uint64_t *out,
+                              unsigned long long cap, int grid,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bitset_emit, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                       A, tile_cnt, tile_pos, out, cap);
+    return hipGetLastError();
+}
+
+}  // namespace pms

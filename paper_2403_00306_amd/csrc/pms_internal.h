@@ -1,0 +1,133 @@
+// pms_internal.h -- structures shared by the host planner and the gfx950
+// kernels of libpms. Not part of the public ABI (include/pms.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pms {
+
+constexpr int kTPB = 256;          // threads per workgroup (4 wave64s)
+constexpr int kWaves = kTPB / 64;
+constexpr int kMaxL = 32;          // one uint32 per bit plane, one uint64 code
+constexpr int kMinSuffix = 3;      // a tile word covers the last 3 bases
+constexpr int kMaxSuffix = 9;      // 4^9 codes per tile = 4096 64-bit words
+constexpr int kMaxWords = 1 << (2 * (kMaxSuffix - 3));
+constexpr int kWordsPerThread = kMaxWords / kTPB;   // 16
+constexpr int kYChunk = 640;       // l-mers staged per marking round
+constexpr int kSurvMax = 256;      // survivor list of the filter stage
+constexpr int kBallDigits = kMaxSuffix - 3;         // 6 word-index digits
+
+// One instance as the kernels see it. All pointers are device memory.
+struct InstDev {
+    const uint8_t *seqs;     // n*m ASCII bytes, row-major
+    uint64_t *packed;        // n*wpr words: base j of a row at bits 2(j%32)
+    uint32_t *phi;           // n*wpr: bit j%32 = high code bit of base j
+    uint32_t *plo;           // n*wpr: bit j%32 = low code bit of base j
+    uint2 *planes;           // n*L l-mers: .x high plane, .y low plane,
+                             //   bit p = base p of the l-mer
+    uint64_t *codes;         // n*L l-mers, first base in the top digit
+    const int *order;        // n: string order of the tile passes
+    unsigned long long *bad; // first bad byte (row*m+col); ~0 if none
+    // tile outputs (tiled path); tile indices are local to the instance
+    uint32_t *tile_cnt;      // ntiles: motifs found in each tile
+    uint64_t *tile_heap_off; // ntiles: where the tile's motifs sit in heap
+    uint64_t *heap;          // unordered blocks of ascending codes
+    unsigned long long *heap_top;
+    unsigned long long heap_cap;
+    uint64_t tile_base;      // first tile of this instance in a batch's
+                             //   concatenated tile space
+    uint64_t ntiles;         // 4^(l-s)
+    int n, m, l, d, L, s, surv_t, wpr;
+};
+
+// A contiguous range of one instance's tiles.
+struct WorkItem {
+    int inst;
+    int pad;
+    uint64_t t0, t1;
+};
+
+// Device counters of the tiled and bitset kernels.
+struct TileStats {
+    unsigned long long passes;      // (tile, string) passes
+    unsigned long long marks;       // 64-bit word ORs
+    unsigned long long ftests;      // Hamming tests of the filter stage
+    unsigned long long tiles;       // tiles finished
+};
+
+// Tables built once per context (device memory).
+struct Tables {
+    // Word-index ball table for q = s-3 digits: all 4^q XOR masks over q
+    // 2-bit digits ordered by weight (number of nonzero digits); entry =
+    // mask | weight << 12. ball_off[q*8 + w] = first entry of weight w
+    // (ball_off[q*8 + q + 1] = 4^q).
+    const uint16_t *ball;        // concatenated for q = 0..6
+    const int *ball_base;        // start of table q in ball[]
+    const int *ball_off;         // 7 x 8 offsets
+    // Word masks: m3[b*4 + t] = bit z set iff the 3-base codes z and b
+    // differ in at most t bases (t = 3: every z).
+    const unsigned long long *m3;
+};
+
+// ---- kernel launchers (defined in the .hip files) -----------------------
+
+// Pack + validate (a1) and l-mer index (a2) for ninst instances.
+hipError_t launch_index(const InstDev *d_insts, int ninst, int max_rows_words,
+                        int max_lmers, hipStream_t st);
+
+// Tiled pattern-driven kernel over a work list (persistent workgroups).
+// d_items == nullptr: instance 0's tiles in nitems chunks of `chunk`.
+hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
+                        int nitems, uint64_t chunk, unsigned int *d_next,
+                        Tables tb, TileStats *stats, int grid, hipStream_t st);
+int tiled_blocks_per_cu();
+
+// Memory-heavy bitset path: one pass per string over the whole 4^l space.
+hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
+                              unsigned long long *A, uint8_t *alive,
+                              TileStats *stats, int grid, hipStream_t st);
+hipError_t launch_bitset_count(const InstDev *d_inst,
+                               const unsigned long long *A,
+                               const uint8_t *alive, uint32_t *tile_cnt,
+                               int grid, hipStream_t st);
+hipError_t launch_bitset_emit(const InstDev *d_inst,
+                              const unsigned long long *A,
+                              const uint32_t *tile_cnt,
+                              const uint64_t *tile_pos, uint64_t *out,
+                              unsigned long long cap, int grid,
+                              hipStream_t st);
+
+// Sample-driven filter path.
+hipError_t launch_masks(int l, int d, uint2 *masks, uint64_t nb,
+                        hipStream_t st);
+hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
+                         uint64_t nb, unsigned long long *next_block,
+                         uint64_t *heap, unsigned long long *heap_top,
+                         unsigned long long heap_cap,
+                         unsigned long long *hc_per_ref, int grid,
+                         hipStream_t st);
+int filter_blocks_per_cu();
+
+// Scans, ordered gathers and sorting (a6).
+size_t scan_scratch_bytes(uint64_t n);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out,
+                           void *scratch, hipStream_t st);
+// Tiles whose block lies beyond heap_cap (heap overflow) are skipped.
+hipError_t launch_gather(const uint32_t *tile_cnt, const uint64_t *heap_off,
+                         const uint64_t *tile_pos, const uint64_t *heap,
+                         uint64_t ntiles, uint64_t *out,
+                         unsigned long long out_cap,
+                         unsigned long long heap_cap, hipStream_t st);
+hipError_t launch_ranges(const InstDev *d_insts, int ninst,
+                         const uint64_t *tile_pos, uint64_t *ranges,
+                         hipStream_t st);
+size_t sort_scratch_bytes(uint64_t n);
+hipError_t launch_sort_u64(uint64_t *keys, uint64_t n, int key_bits,
+                           void *scratch, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v,
+                           hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n,
+                           unsigned long long v, hipStream_t st);
+
+}  // namespace pms

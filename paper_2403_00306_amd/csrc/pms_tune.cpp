@@ -1,0 +1,150 @@
+// pms_tune.cpp -- autotuner for the tiled kernel's tile shape.
+//
+// The tile shape decides how the 4^l code space is cut (suffix length s:
+// 4^s codes per tile, 4^(l-s) tiles) and when a tile stops ANDing sphere
+// unions and starts filtering the codes it has left (surv_t). Neither
+// changes the motif set, only the split of work between marking, prefix
+// tests and Hamming tests. The tuner times every shape on a synthetic
+// uniform-DNA instance of the requested size, checks that every shape
+// returns the same set, and keeps the fastest per (l, d, n-bucket,
+// m-bucket).
+#include "pms_host.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <random>
+
+using namespace pms;
+
+namespace pms {
+
+void load_tune_cache(pms_ctx *c)
+{
+    if (c->tune_path.empty())
+        return;
+    FILE *f = fopen(c->tune_path.c_str(), "r");
+    if (!f)
+        return;
+    unsigned long long key;
+    int s, t;
+    while (fscanf(f, "%llx %d %d", &key, &s, &t) == 3)
+        if (s >= kMinSuffix && s <= kMaxSuffix && t >= 1 && t <= kSurvMax)
+            c->tune[key] = {s, t};
+    fclose(f);
+}
+
+static void save_tune_cache(pms_ctx *c)
+{
+    if (c->tune_path.empty())
+        return;
+    const std::string tmp = c->tune_path + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f)
+        return;
+    for (auto &kv : c->tune)
+        fprintf(f, "%llx %d %d\n", (unsigned long long)kv.first,
+                kv.second.first, kv.second.second);
+    fclose(f);
+    rename(tmp.c_str(), c->tune_path.c_str());
+}
+
+}  // namespace pms
+
+extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
+                            int *best_s, int *best_t)
+{
+    if (!c)
+        return PMS_EINVAL;
+    int rc = check_shape(n, m, l, d);
+    if (rc || l < kMinSuffix)
+        return c->fail(PMS_EINVAL, "autotune: bad shape n=%d m=%d l=%d d=%d",
+                       n, m, l, d);
+    hipSetDevice(c->device);
+    // synthetic uniform DNA (tuning input only)
+    std::mt19937_64 rng(tune_key(l, d, n, m) ^ 0x5eed5eedull);
+    std::vector<char> seqs((size_t)n * m);
+    for (auto &ch : seqs)
+        ch = "ACGT"[rng() & 3];
+
+    std::vector<std::pair<int, int>> cand;
+    const int s_hi = std::min(kMaxSuffix, l);
+    const int s_lo = std::max(kMinSuffix, std::max(l - 12, s_hi - 4));
+    for (int s = s_lo; s <= s_hi; s++)
+        for (int t : {32, 64, 128, 256})
+            cand.push_back({s, t});
+
+    std::pair<int, int> saved;
+    bool had_override;
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        auto it = c->override_cfg.find({l, d});
+        had_override = it != c->override_cfg.end();
+        if (had_override)
+            saved = it->second;
+    }
+    double best = 1e300;
+    std::pair<int, int> pick = cand.front();
+    std::vector<uint64_t> ref, got;
+    bool have_ref = false;
+    int status = PMS_OK;
+    for (auto &cf : cand) {
+        {
+            std::lock_guard<std::mutex> g(c->tune_mu);
+            c->override_cfg[{l, d}] = cf;
+        }
+        double t_min = 1e300;
+        for (int rep = 0; rep < 2 && status == PMS_OK; rep++) {
+            SolveOut r{};
+            rc = solve_core(c, seqs.data(), nullptr, n, m, l, d, c->stream,
+                            nullptr, 0, PMS_PATH_TILED, &r);
+            if (rc) {
+                status = rc;
+                break;
+            }
+            t_min = std::min(t_min, c->last.ms_main + c->last.ms_output);
+            if (rep == 0) {
+                got.resize(r.count);
+                if (r.count &&
+                    hipMemcpy(got.data(), r.d_out, r.count * 8,
+                              hipMemcpyDeviceToHost) != hipSuccess) {
+                    status = c->fail(PMS_EDEVICE, "autotune: copy failed");
+                    break;
+                }
+                if (!have_ref) {
+                    ref = got;
+                    have_ref = true;
+                } else if (got != ref) {
+                    status = c->fail(PMS_EDEVICE, "autotune: tile shape s=%d "
+                                     "t=%d changed the motif set", cf.first,
+                                     cf.second);
+                    break;
+                }
+            }
+        }
+        if (status != PMS_OK)
+            break;
+        if (t_min < best) {
+            best = t_min;
+            pick = cf;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        if (had_override)
+            c->override_cfg[{l, d}] = saved;
+        else
+            c->override_cfg.erase({l, d});
+        if (status == PMS_OK) {
+            c->tune[tune_key(l, d, n, m)] = pick;
+            save_tune_cache(c);
+        }
+    }
+    if (status != PMS_OK)
+        return status;
+    if (best_s)
+        *best_s = pick.first;
+    if (best_t)
+        *best_t = pick.second;
+    return PMS_OK;
+}

@@ -1,0 +1,152 @@
+"""Batched and served forms: every instance's result equals the oracle's and
+the same instance solved alone, bit for bit."""
+import random
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_00306_amd as pms
+import pmsgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_instances(seed, k, classes, nrange, mrange):
+    r = pmsgen.Rng(seed)
+    out = []
+    for _ in range(k):
+        l, d = classes[r.bounded(len(classes))]
+        n = nrange[0] + r.bounded(nrange[1] - nrange[0] + 1)
+        m = mrange[0] + r.bounded(mrange[1] - mrange[0] + 1)
+        out.append(pmsgen.planted(r.next(), n, m, l, d))
+    return out
+
+
+def test_batch_matches_oracle_and_alone():
+    insts = mixed_instances(21, 24, [(7, 1), (9, 2), (11, 3), (8, 2)],
+                            (3, 12), (40, 300))
+    say("batch of", len(insts))
+    with pms.Context() as c:
+        got = c.solve_batch(insts)
+        again = c.solve_batch(insts)      # same shape: graph replay
+        alone = [c.solve(x.seqs, x.n, x.m, x.l, x.d) for x in insts]
+    for i, x in enumerate(insts):
+        want = oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0]
+        np.testing.assert_array_equal(got[i], want, err_msg="inst %d" % i)
+        np.testing.assert_array_equal(again[i], want)
+        np.testing.assert_array_equal(alone[i], want)
+
+
+def test_batch_bad_instance_does_not_spoil_others():
+    insts = mixed_instances(5, 6, [(9, 2), (10, 2)], (4, 8), (50, 120))
+    bad = bytearray(insts[2].seqs)
+    bad[7] = ord("x")
+    items = [(x.seqs, x.n, x.m, x.l, x.d) for x in insts]
+    items[2] = (bytes(bad), insts[2].n, insts[2].m, insts[2].l, insts[2].d)
+    items.append((b"ACGT" * 3, 3, 4, 5, 1))            # l > m: EINVAL
+    items.append((insts[0].seqs[:30 * 3], 3, 30, 30, 2))  # filter path alone
+    with pms.Context() as c:
+        got = c.solve_batch(items)
+    assert isinstance(got[2], pms.PmsError) and got[2].status == pms.PMS_EBASE
+    assert isinstance(got[6], pms.PmsError) and got[6].status == pms.PMS_EINVAL
+    for i in (0, 1, 3, 4, 5, 7):
+        s, n, m, l, d = items[i]
+        np.testing.assert_array_equal(got[i], oracle.o1(s, n, m, l, d)[0])
+
+
+def test_batch_large_output_retry():
+    # two-letter strings give outputs far above the first heap estimate
+    rng = random.Random(2)
+    items = []
+    for k in range(4):
+        n, m, l, d = 3, 200, 9, 3
+        s = bytes(rng.choice(b"AT") for _ in range(n * m))
+        items.append((s, n, m, l, d))
+    with pms.Context() as c:
+        got = c.solve_batch(items)
+        st = c.stats()
+    for i, (s, n, m, l, d) in enumerate(items):
+        np.testing.assert_array_equal(got[i], oracle.o1(s, n, m, l, d)[0])
+    assert st["retries"] >= 1
+
+
+def test_served_requests_match_alone_and_oracle():
+    reqs = mixed_instances(33, 40, [(9, 2), (11, 3), (13, 4), (8, 1)],
+                           (5, 20), (100, 600))
+    with pms.Context(serve_slots=8) as c:
+        tickets = []
+        for i, x in enumerate(reqs):
+            tickets.append(c.submit(x.seqs, x.n, x.m, x.l, x.d))
+            if i % 7 == 0:
+                time.sleep(0.002)   # arrivals while others run
+        res = [c.wait(t, 60000) for t in tickets]
+        times = [c.ticket_times(t) for t in tickets]
+        st = c.serve_stats()
+        for t in tickets:
+            c.release(t)
+        alone = [c.solve(x.seqs, x.n, x.m, x.l, x.d) for x in reqs]
+    assert st["completed"] == len(reqs)
+    assert st["max_inflight"] > 1          # requests overlapped on device
+    for i, x in enumerate(reqs):
+        assert res[i] is not None
+        np.testing.assert_array_equal(res[i], alone[i])
+        np.testing.assert_array_equal(
+            res[i], oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0])
+        ts, ta, td = times[i]
+        assert ts <= ta <= td
+
+
+def test_served_errors_and_queue_limit():
+    x = pmsgen.planted(3, 6, 80, 9, 2)
+    with pms.Context(serve_slots=1, serve_queue=2) as c:
+        with pytest.raises(pms.PmsError) as e:
+            c.submit(x.seqs, 6, 80, 9, 9)
+        assert e.value.status == pms.PMS_EINVAL
+        with pytest.raises(pms.PmsError) as e:
+            c.submit(x.seqs[:6 * 40], 6, 40, 30, 2)   # 4^21 tiles: unsuitable
+        assert e.value.status == pms.PMS_EINVAL
+        bad = bytearray(x.seqs)
+        bad[100] = ord("Z")
+        tb = c.submit(bytes(bad), 6, 80, 9, 2)
+        with pytest.raises(pms.PmsError) as e:
+            c.wait(tb, 60000)
+        assert e.value.status == pms.PMS_EBASE
+        # flood a queue of 2 behind a single slot: some submits must bounce
+        big = pmsgen.planted(4, 20, 600, 13, 4)
+        busy = 0
+        tickets = []
+        for _ in range(40):
+            try:
+                tickets.append(c.submit(big.seqs, 20, 600, 13, 4))
+            except pms.PmsError as err:
+                assert err.status == pms.PMS_EBUSY
+                busy += 1
+        assert busy > 0
+        want = oracle.o1(big.seqs, 20, 600, 13, 4)[0]
+        for t in tickets:
+            np.testing.assert_array_equal(c.wait(t, 120000), want)
+        with pytest.raises(pms.PmsError):
+            c.poll(999999)
+
+
+def test_autotune_picks_a_valid_shape(tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    x = pmsgen.planted(8, 10, 300, 11, 3)
+    want = oracle.o1(x.seqs, 10, 300, 11, 3)[0]
+    with pms.Context(tune_cache=cache) as c:
+        s, t = c.autotune(10, 300, 11, 3)
+        assert 3 <= s <= 9 and 1 <= t <= 256
+        np.testing.assert_array_equal(c.solve(x.seqs, 10, 300, 11, 3), want)
+        assert c.stats()["tile_suffix"] == s
+    # the cache file carries the choice to a new context
+    with pms.Context(tune_cache=cache) as c2:
+        c2.solve(x.seqs, 10, 300, 11, 3)
+        assert c2.stats()["tile_suffix"] == s

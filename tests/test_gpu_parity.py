@@ -1,0 +1,280 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every case compares the ascending uint64 motif codes element by element with
+the oracle on the same seeded input. Small cases span many tiles and a
+ragged tail; the full (9,2) and (13,4) configurations are compared whole;
+(17,6) is checked on properties the oracle can verify at any size (every
+reported code, the plant, path agreement, and completeness on a sample of
+reference l-mers). Integer results: the tolerance is zero.
+"""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_00306_amd as pms
+import pmsgen
+
+pytestmark = pytest.mark.gpu
+
+ACGT = b"ACGT"
+PATHS = [pms.PATH_FILTER, pms.PATH_TILED, pms.PATH_BITSET]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pms.Context()
+    yield c
+    c.close()
+
+
+def code_of(lmer: bytes) -> int:
+    c = 0
+    for ch in lmer:
+        c = 4 * c + ACGT.index(ch)
+    return c
+
+
+def oracle_set(seqs, n, m, l, d):
+    return oracle.o1(seqs, n, m, l, d)[0]
+
+
+def solve_path(path, seqs, n, m, l, d):
+    with pms.Context(path=path) as c:
+        got = c.solve(seqs, n, m, l, d)
+        st = c.stats()
+    return got, st
+
+
+def rand_instance(rng, n, m, alphabet=ACGT):
+    return bytes(rng.choice(alphabet) for _ in range(n * m))
+
+
+# ---------------------------------------------------------------------------
+# small and ragged cases, every path
+# ---------------------------------------------------------------------------
+
+SMALL = [
+    # (n, m, l, d, note)
+    (5, 40, 5, 1, "tiny"),
+    (8, 61, 7, 2, "ragged m"),
+    (6, 33, 6, 0, "d=0"),
+    (1, 30, 6, 2, "n=1: union of spheres"),
+    (4, 8, 8, 3, "m=l"),
+    (7, 95, 9, 2, "several tiles"),
+    (3, 1500, 8, 2, "m above one staging chunk"),
+    (10, 130, 11, 3, "many tiles"),
+    (5, 64, 3, 1, "l=3: one word"),
+    (4, 40, 4, 3, "d=l-1"),
+    (6, 200, 10, 1, "small d"),
+]
+
+
+@pytest.mark.parametrize("n,m,l,d,note", SMALL)
+@pytest.mark.parametrize("path", PATHS)
+def test_small_vs_oracle(path, n, m, l, d, note):
+    rng = random.Random(hash((n, m, l, d)) & 0xffff)
+    seqs = rand_instance(rng, n, m)
+    say("case", note, n, m, l, d, "path", path)
+    want = oracle_set(seqs, n, m, l, d)
+    got, st = solve_path(path, seqs, n, m, l, d)
+    assert st["path"] == path
+    assert got.dtype == np.uint64
+    np.testing.assert_array_equal(got, want)
+
+
+def test_small_vs_bruteforce_o0():
+    rng = random.Random(17)
+    for trial in range(12):
+        l = rng.randint(3, 8)
+        d = rng.randint(0, min(3, l - 1))
+        n = rng.randint(1, 6)
+        m = rng.randint(l, 70)
+        seqs = rand_instance(rng, n, m)
+        want = oracle.o0(seqs, n, m, l, d)
+        for path in PATHS:
+            got, _ = solve_path(path, seqs, n, m, l, d)
+            np.testing.assert_array_equal(got, want, err_msg=str(
+                (trial, path, n, m, l, d)))
+
+
+def test_long_motifs_filter_path():
+    # l up to 32 (one 32-bit word per bit plane); the planner picks the
+    # sample-driven path here
+    for (n, m, l, d) in [(4, 60, 32, 2), (5, 80, 20, 3), (3, 50, 25, 1)]:
+        inst = pmsgen.planted(l * 7 + d, n, m, l, d)
+        want = oracle_set(inst.seqs, n, m, l, d)
+        with pms.Context() as c:
+            got = c.solve(inst.seqs, n, m, l, d)
+        np.testing.assert_array_equal(got, want)
+        assert code_of(inst.motif) in set(int(x) for x in got)
+
+
+def test_low_entropy_inputs_many_motifs():
+    # two-letter strings: large outputs exercise the radix sort and the
+    # output-capacity retry
+    rng = random.Random(5)
+    n, m, l, d = 3, 300, 9, 3
+    seqs = rand_instance(rng, n, m, alphabet=b"AC")
+    want = oracle_set(seqs, n, m, l, d)
+    assert len(want) > 4096
+    for path in PATHS:
+        got, st = solve_path(path, seqs, n, m, l, d)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_n1_huge_output_tiled_and_filter():
+    rng = random.Random(8)
+    n, m, l, d = 1, 400, 10, 3
+    seqs = rand_instance(rng, n, m)
+    want = oracle_set(seqs, n, m, l, d)
+    assert len(want) > 100000
+    for path in (pms.PATH_TILED, pms.PATH_FILTER):
+        got, _ = solve_path(path, seqs, n, m, l, d)
+        np.testing.assert_array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# the thesis-sized configurations (Table 3.2: n = 20, m = 600)
+# ---------------------------------------------------------------------------
+
+def load_golden(name, seed):
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "%s_seed%d.txt" % (name, seed))
+    kv = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = [t.strip() for t in line.split("=", 1)]
+            kv[k] = v
+    return kv, np.array([int(x) for x in kv["motifs"].split(",")],
+                        dtype=np.uint64)
+
+
+@pytest.mark.parametrize("name,seed", [("pms_9_2", 1), ("pms_9_2", 2),
+                                       ("pms_9_2", 3), ("pms_13_4", 1)])
+@pytest.mark.parametrize("path", PATHS)
+def test_full_size_golden(name, seed, path):
+    kv, want = load_golden(name, seed)
+    inst = pmsgen.plain(name, seed)
+    say("full", name, seed, "path", path)
+    got, st = solve_path(path, inst.seqs, inst.n, inst.m, inst.l, inst.d)
+    np.testing.assert_array_equal(got, want)
+    if path == pms.PATH_FILTER:
+        assert st["hcanon"] == int(kv["hcanon"])
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_13_4_more_seeds(seed):
+    inst = pmsgen.plain("pms_13_4", seed)
+    want, h = oracle.o1(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+    for path in (pms.PATH_TILED, pms.PATH_FILTER):
+        got, st = solve_path(path, inst.seqs, inst.n, inst.m, inst.l, inst.d)
+        np.testing.assert_array_equal(got, want)
+        if path == pms.PATH_FILTER:
+            assert st["hcanon"] == h
+
+
+def test_17_6_properties():
+    inst = pmsgen.plain("pms_17_6", 1)
+    n, m, l, d = inst.n, inst.m, inst.l, inst.d
+    say("full 17,6 tiled")
+    tiled, _ = solve_path(pms.PATH_TILED, inst.seqs, n, m, l, d)
+    say("full 17,6 bitset")
+    bitset, _ = solve_path(pms.PATH_BITSET, inst.seqs, n, m, l, d)
+    np.testing.assert_array_equal(tiled, bitset)
+    assert np.all(np.diff(tiled.astype(np.int64)) > 0)
+    # every reported code is a motif (direct check, Definitions 4-5)
+    for c in tiled:
+        assert oracle.is_motif(inst.seqs, n, m, l, d, int(c))
+    assert code_of(inst.motif) in set(int(x) for x in tiled)
+    # completeness on sampled references: what the oracle derives from these
+    # l-mers of s_1 must all be reported; the filter path's per-reference
+    # Hamming-test counts match the oracle's on the same references
+    say("full 17,6 filter")
+    with pms.Context(path=pms.PATH_FILTER) as c:
+        filt = c.solve(inst.seqs, n, m, l, d)
+        per = c.hcanon_per_ref(m - l + 1)
+    np.testing.assert_array_equal(filt, tiled)
+    rng = random.Random(3)
+    refs = sorted(rng.sample(range(m - l + 1), 3)) + [inst.positions[0]]
+    for j in refs:
+        part, h, pr = oracle.o1(inst.seqs, n, m, l, d, ref_begin=j,
+                                ref_end=j + 1, per_ref=True)
+        assert set(int(x) for x in part) <= set(int(x) for x in tiled)
+        assert int(per[j]) == h
+
+
+# ---------------------------------------------------------------------------
+# tile shape invariance, determinism, device entry point, errors
+# ---------------------------------------------------------------------------
+
+def test_tile_shapes_do_not_change_result():
+    inst = pmsgen.planted(4, 12, 300, 11, 3)
+    want = oracle_set(inst.seqs, inst.n, inst.m, 11, 3)
+    with pms.Context(path=pms.PATH_TILED) as c:
+        for s in range(3, 10):
+            for t in (1, 32, 256):
+                c.set_tile_config(11, 3, s, t)
+                got = c.solve(inst.seqs, inst.n, inst.m, 11, 3)
+                np.testing.assert_array_equal(got, want, err_msg="s=%d t=%d"
+                                              % (s, t))
+                assert c.stats()["tile_suffix"] == s
+
+
+def test_repeat_runs_identical(ctx):
+    inst = pmsgen.plain("pms_13_4", 4)
+    a = ctx.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+    for _ in range(3):
+        np.testing.assert_array_equal(
+            ctx.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d), a)
+
+
+def test_solve_device_with_torch_buffers(ctx):
+    import torch
+    inst = pmsgen.plain("pms_13_4", 1)
+    _, want = load_golden("pms_13_4", 1)
+    dev = torch.device("cuda:0")
+    d_seqs = torch.frombuffer(bytearray(inst.seqs), dtype=torch.uint8).to(dev)
+    d_out = torch.zeros(1024, dtype=torch.int64, device=dev)
+    s = torch.cuda.Stream()
+    cnt = ctx.solve_device(d_seqs.data_ptr(), inst.n, inst.m, inst.l, inst.d,
+                           d_out.data_ptr(), 1024, stream=s.cuda_stream)
+    got = d_out[:cnt].cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, want)
+    # capacity too small: PMS_ENOMEM with the size needed
+    small = torch.zeros(2, dtype=torch.int64, device=dev)
+    with pytest.raises(pms.PmsError) as e:
+        ctx.solve_device(d_seqs.data_ptr(), inst.n, inst.m, inst.l, inst.d,
+                         small.data_ptr(), 2)
+    assert e.value.status == pms.PMS_ENOMEM and e.value.needed == len(want)
+
+
+def test_error_paths(ctx):
+    good = pmsgen.planted(1, 4, 30, 6, 1).seqs
+    bad = bytearray(good)
+    bad[2 * 30 + 7] = ord("N")
+    with pytest.raises(pms.PmsError) as e:
+        ctx.solve(bytes(bad), 4, 30, 6, 1)
+    assert e.value.status == pms.PMS_EBASE
+    assert "string 2 at offset 7" in str(e.value)
+    for (n, m, l, d) in [(4, 30, 6, 6), (4, 30, 33, 1), (0, 30, 6, 1),
+                         (4, 5, 6, 1), (4, 30, 6, -1)]:
+        with pytest.raises(pms.PmsError) as e:
+            ctx.solve(b"A" * (n * m), n, m, l, d)
+        assert e.value.status == pms.PMS_EINVAL
+    # the context still works after errors
+    assert len(ctx.solve(good, 4, 30, 6, 1)) >= 1
+    # a budget too small for the buffers is reported, not crashed on
+    with pms.Context(mem_budget_bytes=1 << 20) as small:
+        inst = pmsgen.plain("pms_13_4", 1)
+        with pytest.raises(pms.PmsError) as e:
+            small.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+        assert e.value.status == pms.PMS_ENOMEM
