@@ -29,11 +29,15 @@
 
 namespace pms {
 
-struct TileShared {
+constexpr int kYPer = (kYChunk + kTPB - 1) / kTPB;    // l-mers per thread
+constexpr int kYList = kYChunk + 4 * (kMaxL + 1);      // radius classes
+                                                       // start 4-aligned
+struct __align__(16) TileShared {
     unsigned long long U[kMaxWords];   // the string's union on this tile
     unsigned long long m3[256];        // word masks, copy of Tables::m3
+    uint16_t ball[kMaxWords];          // word-index XOR masks of table q
     union {
-        uint32_t ylist[kYChunk];       // suffix codes of reaching l-mers
+        uint32_t ylist[kYList];        // suffix codes of reaching l-mers
         uint64_t surv[kSurvMax];       // filter stage: codes left
     };
     int rcnt[kMaxL + 1];               // reaching l-mers per radius r
@@ -42,6 +46,9 @@ struct TileShared {
     unsigned long long red64[kWaves];
     unsigned int red32[kWaves];
     unsigned long long bcast;
+    int ball_q;                        // which table sits in ball[]
+    uint8_t hit[kSurvMax];             // filter stage: hit in this string
+    uint8_t alive[kSurvMax];           // filter stage: still a candidate
 };
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -108,9 +115,34 @@ __device__ __forceinline__ void prefix_planes(uint64_t P, int pl,
     }
 }
 
+// Bring ball table q into LDS (once per change of q). Call uniformly.
+__device__ __forceinline__ void load_ball(TileShared &sh, const Tables &tb,
+                                          int q)
+{
+    __syncthreads();
+    if (sh.ball_q == q)
+        return;
+    const uint16_t *src = tb.ball + tb.ball_base[q];
+    const int nq = 1 << (2 * q);
+    for (int i = threadIdx.x; i < nq; i += kTPB)
+        sh.ball[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        sh.ball_q = q;
+    __syncthreads();
+}
+
 // OR into sh.U the union of the d-spheres of string `seq`'s l-mers,
-// restricted to the tile with prefix planes (Phi, Plo). Ends with a barrier.
-// Returns (in thread 0) the number of word ORs done.
+// restricted to the tile with prefix planes (Phi, Plo). The ball table of
+// q = s-3 must be in sh.ball. Ends with a barrier. Returns the number of
+// word ORs done (same value in every thread).
+//
+// The reaching l-mers are grouped by radius r and every class is marked
+// entry-parallel: each lane keeps one XOR mask of the class's word-level
+// sphere in registers and walks the class's l-mers. When the sphere has at
+// least kTPB entries the whole group walks the same l-mer (read once by
+// broadcast into scalar registers); a smaller sphere is repeated in
+// 256/bs lane groups that walk different l-mers.
 __device__ unsigned long long mark_string(const InstDev &I, int seq,
                                           uint32_t Phi, uint32_t Plo,
                                           uint32_t premask, TileShared &sh,
@@ -121,7 +153,6 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
     const uint2 *yp = I.planes + (size_t)seq * I.L;
     const uint64_t *yc = I.codes + (size_t)seq * I.L;
     const uint32_t sufmask = (1u << (2 * s)) - 1u;
-    const uint16_t *ball = tb.ball + tb.ball_base[q];
     const int *boff = tb.ball_off + q * 8;
     unsigned long long marks = 0;
     for (int y0 = 0; y0 < I.L; y0 += kYChunk) {
@@ -129,11 +160,21 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
         if (tid <= d)
             sh.rcnt[tid] = 0;
         __syncthreads();
-        for (int j = tid; j < ny; j += kTPB) {
-            const uint2 y = yp[y0 + j];
-            const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
-            if (k <= d)
-                atomicAdd(&sh.rcnt[d - k], 1);
+        uint32_t ys[kYPer];
+        int rr[kYPer];
+#pragma unroll
+        for (int u = 0; u < kYPer; u++) {
+            const int j = tid + u * kTPB;
+            rr[u] = -1;
+            if (j < ny) {
+                const uint2 y = yp[y0 + j];
+                const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
+                if (k <= d) {
+                    rr[u] = d - k;
+                    ys[u] = (uint32_t)yc[y0 + j] & sufmask;
+                    atomicAdd(&sh.rcnt[d - k], 1);
+                }
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -141,19 +182,15 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
             for (int r = 0; r <= d; r++) {
                 sh.roff[r] = acc;
                 sh.rpos[r] = acc;
-                acc += sh.rcnt[r];
+                acc += (sh.rcnt[r] + 3) & ~3;
             }
             sh.roff[d + 1] = acc;
         }
         __syncthreads();
-        for (int j = tid; j < ny; j += kTPB) {
-            const uint2 y = yp[y0 + j];
-            const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
-            if (k <= d) {
-                const int p = atomicAdd(&sh.rpos[d - k], 1);
-                sh.ylist[p] = (uint32_t)yc[y0 + j] & sufmask;
-            }
-        }
+#pragma unroll
+        for (int u = 0; u < kYPer; u++)
+            if (rr[u] >= 0)
+                sh.ylist[atomicAdd(&sh.rpos[rr[u]], 1)] = ys[u];
         __syncthreads();
         for (int r = 0; r <= d; r++) {
             const int c = sh.rcnt[r];
@@ -161,22 +198,64 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 continue;
             const int rw = min(r, q);
             const uint32_t bs = (uint32_t)boff[rw + 1];
-            const uint32_t total = (uint32_t)c * bs;
-            const uint64_t magic = (0x100000000ull + bs - 1) / bs;
             const uint32_t *yl = sh.ylist + sh.roff[r];
-            marks += total;
-            for (uint32_t f = tid; f < total; f += kTPB) {
-                uint32_t yi = (uint32_t)(((uint64_t)f * magic) >> 32);
-                int e = (int)(f - yi * bs);
-                if (e < 0) {
-                    yi--;
-                    e += (int)bs;
+            marks += (unsigned long long)c * bs;
+            // rotate the lane assignment per class so that the lanes a
+            // class leaves idle fall in a different wave each time
+            const uint32_t vt = (uint32_t)(tid + 64 * r) & (uint32_t)(kTPB - 1);
+            if (bs >= (uint32_t)kTPB) {
+                // every lane owns entries vt, vt+256, ...; the l-mer is
+                // the same for the whole wave (scalar registers)
+                for (uint32_t e = vt; e < bs; e += kTPB) {
+                    const uint32_t ent = sh.ball[e];
+                    const uint32_t mask = ent & 0xfffu;
+                    const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
+                    const unsigned long long *mt = sh.m3 + tt;
+                    int yi = 0;
+                    for (; yi + 4 <= c; yi += 4) {
+                        const uint4 y4 = *(const uint4 *)(yl + yi);
+                        const uint32_t a0 = __builtin_amdgcn_readfirstlane(y4.x);
+                        const uint32_t a1 = __builtin_amdgcn_readfirstlane(y4.y);
+                        const uint32_t a2 = __builtin_amdgcn_readfirstlane(y4.z);
+                        const uint32_t a3 = __builtin_amdgcn_readfirstlane(y4.w);
+                        const unsigned long long m0 = mt[(a0 & 63u) * 4u];
+                        const unsigned long long m1 = mt[(a1 & 63u) * 4u];
+                        const unsigned long long m2 = mt[(a2 & 63u) * 4u];
+                        const unsigned long long m3v = mt[(a3 & 63u) * 4u];
+                        atomicOr(&sh.U[(a0 >> 6) ^ mask], m0);
+                        atomicOr(&sh.U[(a1 >> 6) ^ mask], m1);
+                        atomicOr(&sh.U[(a2 >> 6) ^ mask], m2);
+                        atomicOr(&sh.U[(a3 >> 6) ^ mask], m3v);
+                    }
+                    for (; yi < c; yi++) {
+                        const uint32_t y = __builtin_amdgcn_readfirstlane(yl[yi]);
+                        atomicOr(&sh.U[(y >> 6) ^ mask], mt[(y & 63u) * 4u]);
+                    }
                 }
-                const uint32_t ys = yl[yi];
-                const uint32_t ent = ball[e];
-                const int tt = min(r - (int)(ent >> 12), 3);
-                const uint32_t widx = (ys >> 6) ^ (ent & 0xfffu);
-                atomicOr(&sh.U[widx], sh.m3[(ys & 63u) * 4u + (uint32_t)tt]);
+            } else {
+                // G = 256/bs groups of bs lanes: each lane owns one entry
+                // and its group walks every G-th l-mer of the class
+                const uint32_t G = (uint32_t)kTPB / bs;
+                const uint32_t slot = vt / bs;
+                const uint32_t e = vt - slot * bs;
+                if (slot < G) {
+                    const uint32_t ent = sh.ball[e];
+                    const uint32_t mask = ent & 0xfffu;
+                    const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
+                    const unsigned long long *mt = sh.m3 + tt;
+                    uint32_t yi = slot;
+                    for (; yi + G < (uint32_t)c; yi += 2 * G) {
+                        const uint32_t y0 = yl[yi], y1 = yl[yi + G];
+                        const unsigned long long m0 = mt[(y0 & 63u) * 4u];
+                        const unsigned long long m1 = mt[(y1 & 63u) * 4u];
+                        atomicOr(&sh.U[(y0 >> 6) ^ mask], m0);
+                        atomicOr(&sh.U[(y1 >> 6) ^ mask], m1);
+                    }
+                    if (yi < (uint32_t)c) {
+                        const uint32_t y = yl[yi];
+                        atomicOr(&sh.U[(y >> 6) ^ mask], mt[(y & 63u) * 4u]);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -313,45 +392,67 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     }
 
     // ---- filter stage: test the few codes left against the rest --------
+    // Survivors are dealt to the waves in groups of 64 (one per lane); when
+    // there are fewer groups than waves, each group's l-mer range is split
+    // across several waves and their hits are ORed in LDS.
     emit_words(sh, W, t, s, sh.surv, true, sh.red32);
+    if (tid < kSurvMax) {
+        sh.hit[tid] = 0;
+        sh.alive[tid] = tid < (int)total;
+    }
     __syncthreads();
     const int nsurv = (int)total;
-    const bool have = tid < nsurv;
+    const int wid = tid >> 6, lane = tid & 63;
+    const int groups = (nsurv + 63) >> 6;                 // 1..4
+    const int parts = kWaves / groups;                    // y-range splits
+    const int grp = wid % groups, part = wid / groups;
+    const int si_ = grp * 64 + lane;                      // my survivor
+    const bool mine_slot = part < parts && si_ < nsurv;
     uint2 cp = make_uint2(0, 0);
-    if (have)
-        cp = code_planes(sh.surv[tid], I.l);
-    bool alive = have;
-    const bool wave_has = __ballot(have) != 0;
+    if (mine_slot)
+        cp = code_planes(sh.surv[si_], I.l);
+    bool alive = tid < nsurv;                              // survivor tid
     for (int sj = si + 1; sj < I.n; sj++) {
         const int nalive = __syncthreads_count(alive);
         if (nalive == 0)
             break;
         if (tid == 0)
             acc.ftests += (unsigned long long)nalive * (unsigned long long)I.L;
-        if (wave_has && __ballot(alive) != 0) {
+        const bool mine = mine_slot && sh.alive[si_];
+        if (__ballot(mine) != 0) {
             const uint2 *yp = I.planes + (size_t)I.order[sj] * I.L;
+            const int j0 = (I.L * part) / parts;
+            const int j1 = (I.L * (part + 1)) / parts;
             uint32_t mind = 255;
-            int j = 0;
-            for (; j + 8 <= I.L; j += 8) {
+            int j = j0;
+            for (; j + 16 <= j1; j += 16) {
 #pragma unroll
-                for (int u = 0; u < 8; u += 2) {
+                for (int u = 0; u < 16; u += 2) {
                     const uint2 y0 = yp[j + u], y1 = yp[j + u + 1];
                     const uint32_t h0 = __popc((cp.x ^ y0.x) | (cp.y ^ y0.y));
                     const uint32_t h1 = __popc((cp.x ^ y1.x) | (cp.y ^ y1.y));
                     mind = min(mind, min(h0, h1));
                 }
-                if (__all(!alive || mind <= (uint32_t)I.d))
+                if (__all(!mine || mind <= (uint32_t)I.d))
                     break;
             }
-            if (j + 8 > I.L) {
-                for (; j < I.L; j++) {
+            if (j + 16 > j1) {
+                for (; j < j1; j++) {
                     const uint2 y = yp[j];
                     mind = min(mind, (uint32_t)__popc((cp.x ^ y.x) |
                                                       (cp.y ^ y.y)));
                 }
             }
-            alive = alive && mind <= (uint32_t)I.d;
+            if (mine && mind <= (uint32_t)I.d)
+                sh.hit[si_] = 1;
         }
+        __syncthreads();
+        if (tid < nsurv) {
+            alive = alive && sh.hit[tid];
+            sh.hit[tid] = 0;
+        }
+        if (tid < kSurvMax)
+            sh.alive[tid] = alive;
     }
     // ordered compaction of the survivors into the heap
     unsigned int ntot;
@@ -378,6 +479,8 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
     __shared__ int s_item;
     for (int i = threadIdx.x; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
+    if (threadIdx.x == 0)
+        sh.ball_q = -1;
     StatAcc acc = {0, 0, 0, 0};
     for (;;) {
         __syncthreads();
@@ -397,6 +500,7 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
             w.t1 = min(w.t0 + chunk, insts[0].ntiles);
         }
         const InstDev I = insts[w.inst];
+        load_ball(sh, tb, I.s - 3);
         for (uint64_t t = w.t0; t < w.t1; t++)
             run_tile(I, t, sh, tb, acc);
     }
@@ -444,6 +548,9 @@ k_bitset_pass(const InstDev *inst, int pass, Tables tb,
     const int seq = I.order[pass];
     for (int i = tid; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
+    if (tid == 0)
+        sh.ball_q = -1;
+    load_ball(sh, tb, q);
     unsigned long long marks = 0, passes = 0;
     for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
         if (pass > 0 && !alive[t])

@@ -313,8 +313,26 @@ void build_tables(std::vector<uint16_t> &ball, std::vector<int> &base,
                 c += e.first < w;
             off[q * 8 + w] = c;
         }
-        for (auto &e : v)
-            ball.push_back((uint16_t)(e.second | (e.first << 12)));
+        // Within each weight, deal the masks out round-robin by their low
+        // six bits: a wave's 64 lanes then take masks with distinct word
+        // residues, XOR with the l-mer's word index keeps them distinct,
+        // and the 64-bit word ORs of one instruction fall in distinct LDS
+        // bank pairs.
+        for (int w = 0; w <= q; w++) {
+            std::vector<std::vector<int>> byres(64);
+            for (int i = off[q * 8 + w]; i < off[q * 8 + w + 1]; i++)
+                byres[v[i].second & 63].push_back(v[i].second);
+            for (size_t k = 0;; k++) {
+                bool any = false;
+                for (int r = 0; r < 64; r++)
+                    if (k < byres[r].size()) {
+                        ball.push_back((uint16_t)(byres[r][k] | (w << 12)));
+                        any = true;
+                    }
+                if (!any)
+                    break;
+            }
+        }
     }
     m3.assign(256, 0);
     for (int b = 0; b < 64; b++)
