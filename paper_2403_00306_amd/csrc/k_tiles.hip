@@ -115,6 +115,29 @@ __device__ __forceinline__ void prefix_planes(uint64_t P, int pl,
     }
 }
 
+// LDS position of tile word w: the bank bits (low 5 bits of the word
+// position) take the XOR of the word index's low 5 bits with its higher
+// bit groups, so words that differ only in high digits still fall in
+// different banks. A bijection on [0, 4^q) that keeps bits 5 and up.
+__device__ __forceinline__ uint32_t wpos(uint32_t w)
+{
+    return w ^ ((w >> 5) & 31u) ^ ((w >> 10) & 31u);
+}
+
+// OR a single bit (bit b of tile word w) with a 32-bit atomic on the half
+// that holds it: one LDS bank per lane instead of two.
+__device__ __forceinline__ void or_bit(TileShared &sh, uint32_t w, uint32_t b)
+{
+    atomicOr(reinterpret_cast<unsigned int *>(sh.U) + 2u * wpos(w) + (b >> 5),
+             1u << (b & 31u));
+}
+
+__device__ __forceinline__ void or_word(TileShared &sh, uint32_t w,
+                                        unsigned long long m)
+{
+    atomicOr(&sh.U[wpos(w)], m);
+}
+
 // Bring ball table q into LDS (once per change of q). Call uniformly.
 __device__ __forceinline__ void load_ball(TileShared &sh, const Tables &tb,
                                           int q)
@@ -212,6 +235,26 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
                     const unsigned long long *mt = sh.m3 + tt;
                     int yi = 0;
+                    if (__ballot(tt != 0) == 0) {
+                        // the whole wave has in-word radius 0: the word mask
+                        // is the single bit of the l-mer's last 3 bases
+                        for (; yi + 4 <= c; yi += 4) {
+                            const uint4 y4 = *(const uint4 *)(yl + yi);
+                            const uint32_t a0 = __builtin_amdgcn_readfirstlane(y4.x);
+                            const uint32_t a1 = __builtin_amdgcn_readfirstlane(y4.y);
+                            const uint32_t a2 = __builtin_amdgcn_readfirstlane(y4.z);
+                            const uint32_t a3 = __builtin_amdgcn_readfirstlane(y4.w);
+                            or_bit(sh, (a0 >> 6) ^ mask, a0 & 63u);
+                            or_bit(sh, (a1 >> 6) ^ mask, a1 & 63u);
+                            or_bit(sh, (a2 >> 6) ^ mask, a2 & 63u);
+                            or_bit(sh, (a3 >> 6) ^ mask, a3 & 63u);
+                        }
+                        for (; yi < c; yi++) {
+                            const uint32_t y = __builtin_amdgcn_readfirstlane(yl[yi]);
+                            or_bit(sh, (y >> 6) ^ mask, y & 63u);
+                        }
+                        continue;
+                    }
                     for (; yi + 4 <= c; yi += 4) {
                         const uint4 y4 = *(const uint4 *)(yl + yi);
                         const uint32_t a0 = __builtin_amdgcn_readfirstlane(y4.x);
@@ -222,14 +265,14 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                         const unsigned long long m1 = mt[(a1 & 63u) * 4u];
                         const unsigned long long m2 = mt[(a2 & 63u) * 4u];
                         const unsigned long long m3v = mt[(a3 & 63u) * 4u];
-                        atomicOr(&sh.U[(a0 >> 6) ^ mask], m0);
-                        atomicOr(&sh.U[(a1 >> 6) ^ mask], m1);
-                        atomicOr(&sh.U[(a2 >> 6) ^ mask], m2);
-                        atomicOr(&sh.U[(a3 >> 6) ^ mask], m3v);
+                        or_word(sh, (a0 >> 6) ^ mask, m0);
+                        or_word(sh, (a1 >> 6) ^ mask, m1);
+                        or_word(sh, (a2 >> 6) ^ mask, m2);
+                        or_word(sh, (a3 >> 6) ^ mask, m3v);
                     }
                     for (; yi < c; yi++) {
                         const uint32_t y = __builtin_amdgcn_readfirstlane(yl[yi]);
-                        atomicOr(&sh.U[(y >> 6) ^ mask], mt[(y & 63u) * 4u]);
+                        or_word(sh, (y >> 6) ^ mask, mt[(y & 63u) * 4u]);
                     }
                 }
             } else {
@@ -244,16 +287,29 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
                     const unsigned long long *mt = sh.m3 + tt;
                     uint32_t yi = slot;
+                    if (__ballot(tt != 0) == 0) {
+                        // in-word radius 0 in every active lane: single bit
+                        for (; yi + G < (uint32_t)c; yi += 2 * G) {
+                            const uint32_t y0 = yl[yi], y1 = yl[yi + G];
+                            or_bit(sh, (y0 >> 6) ^ mask, y0 & 63u);
+                            or_bit(sh, (y1 >> 6) ^ mask, y1 & 63u);
+                        }
+                        if (yi < (uint32_t)c) {
+                            const uint32_t y = yl[yi];
+                            or_bit(sh, (y >> 6) ^ mask, y & 63u);
+                        }
+                        continue;
+                    }
                     for (; yi + G < (uint32_t)c; yi += 2 * G) {
                         const uint32_t y0 = yl[yi], y1 = yl[yi + G];
                         const unsigned long long m0 = mt[(y0 & 63u) * 4u];
                         const unsigned long long m1 = mt[(y1 & 63u) * 4u];
-                        atomicOr(&sh.U[(y0 >> 6) ^ mask], m0);
-                        atomicOr(&sh.U[(y1 >> 6) ^ mask], m1);
+                        or_word(sh, (y0 >> 6) ^ mask, m0);
+                        or_word(sh, (y1 >> 6) ^ mask, m1);
                     }
                     if (yi < (uint32_t)c) {
                         const uint32_t y = yl[yi];
-                        atomicOr(&sh.U[(y >> 6) ^ mask], mt[(y & 63u) * 4u]);
+                        or_word(sh, (y >> 6) ^ mask, mt[(y & 63u) * 4u]);
                     }
                 }
             }
@@ -341,7 +397,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         for (int k = 0; k < kWordsPerThread; k++) {
             const int w = tid + k * kTPB;
             if (w < W) {
-                const unsigned long long u = sh.U[w];
+                const unsigned long long u = sh.U[wpos((uint32_t)w)];
                 A[k] = (si == 0) ? u : (A[k] & u);
                 cnt += __popcll(A[k]);
             }
@@ -565,7 +621,7 @@ k_bitset_pass(const InstDev *inst, int pass, Tables tb,
         unsigned long long *Ag = A + t * (uint64_t)W;
         int nz = 0;
         for (int w = tid; w < W; w += kTPB) {
-            const unsigned long long u = sh.U[w];
+            const unsigned long long u = sh.U[wpos((uint32_t)w)];
             const unsigned long long a = pass ? (Ag[w] & u) : u;
             Ag[w] = a;
             nz |= (a != 0);
