@@ -115,14 +115,14 @@ __device__ __forceinline__ unsigned int blk_exscan(unsigned int v,
             before += red[w];
         tot += red[w];
     }
-    *total = tot;
+    *total = uni(tot);
     return before + x - v;
 }
 
 // Minimum distance from each of the thread's candidates to the l-mers of
 // one string; the l-mer is the same for the whole wave (scalar loads).
 template <int K>
-__device__ __forceinline__ void scan_string(const uint2 *yp, int L,
+__device__ __forceinline__ void scan_string(const PlaneRow yp, int L,
                                             const uint2 (&c)[K],
                                             uint32_t (&mind)[K], int d,
                                             unsigned int live_mask)
@@ -165,7 +165,7 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
     const InstDev I = *inst;
     const int tid = threadIdx.x;
     const int L = I.L, d = I.d, l = I.l;
-    const uint2 *x_planes = I.planes;                // row 0 = s_1
+    const PlaneRow x_planes = planes_row(I.planes, 0);   // row 0 = s_1
     const uint64_t total = (uint64_t)L * nb;
     const uint64_t nblocks = (total + kFBlock - 1) / kFBlock;
 
@@ -174,7 +174,7 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         if (tid == 0)
             sh.blk = atomicAdd(next_block, 1ull);
         __syncthreads();
-        const uint64_t b = sh.blk;
+        const uint64_t b = uni(sh.blk);
         if (b >= nblocks)
             break;
         const uint64_t f0 = b * kFBlock;
@@ -205,7 +205,7 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
 
         int nlive = kFBlock;   // upper bound; slots carry live bits
         for (int si = 1; si < I.n && nlive > 0; si++) {
-            const uint2 *yp = I.planes + (size_t)si * L;
+            const PlaneRow yp = planes_row(I.planes, (size_t)si * L);
             uint32_t mind[kFPer];
 #pragma unroll
             for (int k = 0; k < kFPer; k++) {
@@ -270,7 +270,7 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
             sh.off = atomicAdd(heap_top, (unsigned long long)tot);
         __syncthreads();
         if (tot) {
-            const unsigned long long off = sh.off;
+            const unsigned long long off = uni(sh.off);
             unsigned int w = pos;
 #pragma unroll
             for (int k = 0; k < kFPer; k++)

@@ -72,7 +72,7 @@ block_sum64(unsigned long long v, unsigned long long *red)
 #pragma unroll
     for (int w = 0; w < kWaves; w++)
         t += red[w];
-    return t;
+    return uni(t);
 }
 
 // Exclusive prefix sum over the workgroup in thread order.
@@ -98,7 +98,7 @@ block_exscan(unsigned int v, unsigned int *red, unsigned int *total)
             before += red[w];
         tot += red[w];
     }
-    *total = tot;
+    *total = uni(tot);
     return before + x - v;
 }
 
@@ -143,7 +143,7 @@ __device__ __forceinline__ void load_ball(TileShared &sh, const Tables &tb,
                                           int q)
 {
     __syncthreads();
-    if (sh.ball_q == q)
+    if (uni(sh.ball_q) == q)
         return;
     const uint16_t *src = tb.ball + tb.ball_base[q];
     const int nq = 1 << (2 * q);
@@ -173,8 +173,8 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
 {
     const int tid = threadIdx.x;
     const int d = I.d, s = I.s, q = s - 3;
-    const uint2 *yp = I.planes + (size_t)seq * I.L;
-    const uint64_t *yc = I.codes + (size_t)seq * I.L;
+    const PlaneRow yp = planes_row(I.planes, (size_t)seq * I.L);
+    const g_u64 *yc = gptr(I.codes) + (size_t)seq * I.L;
     const uint32_t sufmask = (1u << (2 * s)) - 1u;
     const int *boff = tb.ball_off + q * 8;
     unsigned long long marks = 0;
@@ -216,12 +216,12 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 sh.ylist[atomicAdd(&sh.rpos[rr[u]], 1)] = ys[u];
         __syncthreads();
         for (int r = 0; r <= d; r++) {
-            const int c = sh.rcnt[r];
+            const int c = uni(sh.rcnt[r]);
             if (c == 0)
                 continue;
             const int rw = min(r, q);
             const uint32_t bs = (uint32_t)boff[rw + 1];
-            const uint32_t *yl = sh.ylist + sh.roff[r];
+            const uint32_t *yl = sh.ylist + uni(sh.roff[r]);
             marks += (unsigned long long)c * bs;
             // rotate the lane assignment per class so that the lanes a
             // class leaves idle fall in a different wave each time
@@ -386,7 +386,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     int si = 0;
     bool to_filter = false;
     for (si = 0; si < I.n; si++) {
-        const int seq = I.order[si];
+        const int seq = uni(I.order[si]);
         for (int w = tid; w < W; w += kTPB)
             sh.U[w] = 0;
         __syncthreads();
@@ -441,7 +441,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             tile_heap_off[g] = off;
         }
         __syncthreads();
-        const unsigned long long off = sh.bcast;
+        const unsigned long long off = uni(sh.bcast);
         const bool fits = off + total <= heap_cap;
         emit_words(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
         return;
@@ -458,7 +458,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     }
     __syncthreads();
     const int nsurv = (int)total;
-    const int wid = tid >> 6, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int groups = (nsurv + 63) >> 6;                 // 1..4
     const int parts = kWaves / groups;                    // y-range splits
     const int grp = wid % groups, part = wid / groups;
@@ -469,21 +469,22 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         cp = code_planes(sh.surv[si_], I.l);
     bool alive = tid < nsurv;                              // survivor tid
     for (int sj = si + 1; sj < I.n; sj++) {
-        const int nalive = __syncthreads_count(alive);
+        const int nalive = uni(__syncthreads_count(alive));
         if (nalive == 0)
             break;
         if (tid == 0)
             acc.ftests += (unsigned long long)nalive * (unsigned long long)I.L;
         const bool mine = mine_slot && sh.alive[si_];
         if (__ballot(mine) != 0) {
-            const uint2 *yp = I.planes + (size_t)I.order[sj] * I.L;
+            const PlaneRow yp = planes_row(I.planes,
+                                           (size_t)uni(I.order[sj]) * I.L);
             const int j0 = (I.L * part) / parts;
             const int j1 = (I.L * (part + 1)) / parts;
             uint32_t mind = 255;
             int j = j0;
-            for (; j + 16 <= j1; j += 16) {
+            for (; j + 32 <= j1; j += 32) {
 #pragma unroll
-                for (int u = 0; u < 16; u += 2) {
+                for (int u = 0; u < 32; u += 2) {
                     const uint2 y0 = yp[j + u], y1 = yp[j + u + 1];
                     const uint32_t h0 = __popc((cp.x ^ y0.x) | (cp.y ^ y0.y));
                     const uint32_t h1 = __popc((cp.x ^ y1.x) | (cp.y ^ y1.y));
@@ -492,7 +493,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 if (__all(!mine || mind <= (uint32_t)I.d))
                     break;
             }
-            if (j + 16 > j1) {
+            if (j + 32 > j1) {
                 for (; j < j1; j++) {
                     const uint2 y = yp[j];
                     mind = min(mind, (uint32_t)__popc((cp.x ^ y.x) |
@@ -543,7 +544,7 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
         if (threadIdx.x == 0)
             s_item = (int)atomicAdd(next, 1u);
         __syncthreads();
-        const int it = s_item;
+        const int it = uni(s_item);
         if (it >= nitems)
             break;
         WorkItem w;

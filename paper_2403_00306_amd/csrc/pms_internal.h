@@ -18,6 +18,47 @@ constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
 constexpr int kBallDigits = kMaxSuffix - 3;         // 6 word-index digits
 
+// Read-only views of device arrays held in descriptors. The l-mer tables
+// are written by the index kernels and only read afterwards, so kernels
+// may read them through the constant address space: wave-uniform loads
+// then become scalar loads and the rest global (not flat) loads. Bit-plane
+// pairs are read as one 64-bit word (.x in the low half).
+typedef __attribute__((address_space(4))) const unsigned long long g_u64;
+struct PlaneRow {
+    const g_u64 *p;
+    __device__ __forceinline__ uint2 operator[](size_t i) const
+    {
+        const unsigned long long v = p[i];
+        return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+};
+__device__ __forceinline__ PlaneRow planes_row(const uint2 *base, size_t off)
+{
+    return PlaneRow{(const g_u64 *)(const void *)(base + off)};
+}
+__device__ __forceinline__ const g_u64 *gptr(const uint64_t *p)
+{
+    return (const g_u64 *)(const void *)p;
+}
+
+// Values that are the same in every lane by construction (block-reduction
+// results, counts read back from LDS after a barrier): tell the compiler,
+// so that loops over them stay scalar.
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int uni(int v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ unsigned long long uni(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // One instance as the kernels see it. All pointers are device memory.
 struct InstDev {
     const uint8_t *seqs;     // n*m ASCII bytes, row-major
