@@ -58,6 +58,97 @@ def cpu_baseline(inst, target_s: float = 12.0) -> dict:
                       % (k, L, t, h)}
 
 
+def batch_bench(pms, pmsgen, np, tune: bool) -> dict:
+    """256 independent instances: one pms_solve_batch call (one persistent
+    launch, replayed as a HIP graph) vs the same instances solved one by
+    one with pms_solve, on the same context."""
+    insts = pmsgen.batched(seed=7, count=256)
+    ctx = pms.Context(device=0)
+    t_tune = 0.0
+    if tune:
+        t0 = time.perf_counter()
+        seen = set()
+        for x in insts:
+            key = (x.l, x.d, x.n.bit_length(), x.m.bit_length())
+            if key not in seen:
+                seen.add(key)
+                ctx.autotune(x.n, x.m, x.l, x.d)
+        t_tune = time.perf_counter() - t0
+    ctx.solve_batch(insts)                       # warm-up + graph capture
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = ctx.solve_batch(insts)
+    t_batch = (time.perf_counter() - t0) / reps
+    bst = ctx.stats()
+    t0 = time.perf_counter()
+    alone = [ctx.solve(x.seqs, x.n, x.m, x.l, x.d) for x in insts]
+    t_plain = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(got, alone))
+    ctx.close()
+    return {"instances": len(insts), "batched_instances_per_s":
+            len(insts) / t_batch, "plain_instances_per_s":
+            len(insts) / t_plain, "batched_ms": 1000 * t_batch,
+            "plain_ms": 1000 * t_plain, "batch_kernel_ms": bst["ms_main"],
+            "motifs_total": int(sum(len(a) for a in alone)),
+            "batched_equals_plain": bool(same), "autotune_s": t_tune}
+
+
+def serve_bench(pms, pmsgen, np, count: int) -> dict:
+    """Poisson request stream through the continuous-batching engine:
+    first a saturation pass (all requests at t=0) gives the capacity C;
+    then an open-loop pass at rate 0.8*C reports p50/p99 latency."""
+    reqs = pmsgen.served(seed=11, count=count)
+
+    def run(rate):
+        ctx = pms.Context(device=0, serve_slots=64)
+        t_start = ctx.clock_ms()
+        tickets = []
+        for r in reqs:
+            if rate:
+                due = t_start + 1000.0 * r.arrival_unit / rate
+                while ctx.clock_ms() < due:
+                    time.sleep(max(0.0, (due - ctx.clock_ms()) / 1000.0 - 2e-4))
+            x = r.inst
+            tickets.append((ctx.submit(x.seqs, x.n, x.m, x.l, x.d),
+                            t_start + (1000.0 * r.arrival_unit / rate
+                                       if rate else 0.0)))
+        results, lat = [], []
+        t_last = t_start
+        for tk, t_arr in tickets:
+            res = ctx.wait(tk, 600000)
+            ts, ta, td = ctx.ticket_times(tk)
+            lat.append(td - t_arr)      # completion - (scheduled) arrival
+            t_last = max(t_last, td)
+            results.append(res)
+            ctx.release(tk)
+        st = ctx.serve_stats()
+        ctx.close()
+        return results, np.array(lat), (t_last - t_start) / 1000.0, st
+
+    res_sat, lat_sat, span_sat, st_sat = run(0.0)
+    cap = len(reqs) / span_sat
+    rate = 0.8 * cap
+    res, lat, span, st = run(rate)
+    same = all(np.array_equal(a, b) for a, b in zip(res, res_sat))
+    # a sample solved alone must equal its served result
+    ctx = pms.Context(device=0)
+    idx = list(range(0, len(reqs), max(1, len(reqs) // 50)))
+    alone_ok = all(np.array_equal(ctx.solve(reqs[i].inst.seqs, reqs[i].inst.n,
+                                            reqs[i].inst.m, reqs[i].inst.l,
+                                            reqs[i].inst.d), res[i])
+                   for i in idx)
+    ctx.close()
+    return {"requests": len(reqs), "capacity_instances_per_s": cap,
+            "rate_per_s": rate, "instances_per_s": len(reqs) / span,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "saturation_p50_ms": float(np.percentile(lat_sat, 50)),
+            "max_inflight": int(st["max_inflight"]),
+            "launches": int(st["launches"]),
+            "mix_equals_saturated_and_alone": bool(same and alone_ok)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +157,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not "
@@ -150,6 +245,14 @@ def main():
             "frac_hbm": bst["bytes_main"] / (bst["ms_main"] / 1000.0)
             / PEAK_HBM}
         bctx.close()
+    if not args.no_batch:
+        log("batched")
+        extra["batched"] = batch_bench(pms, pmsgen, np, not args.no_tune)
+        log(json.dumps(extra["batched"]))
+    if not args.no_serve:
+        log("served")
+        extra["served"] = serve_bench(pms, pmsgen, np, args.serve_count)
+        log(json.dumps(extra["served"]))
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")

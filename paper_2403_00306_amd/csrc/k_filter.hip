@@ -119,13 +119,25 @@ __device__ __forceinline__ unsigned int blk_exscan(unsigned int v,
     return before + x - v;
 }
 
-// Minimum distance from each of the thread's candidates to the l-mers of
-// one string; the l-mer is the same for the whole wave (scalar loads).
+// One string's l-mers read with wave-uniform addresses through the global
+// address space (the loads broadcast one 16-byte row to the wave; on this
+// loop they measured faster than scalar loads, which must all land before
+// any use).
+struct BRow {
+    const __attribute__((address_space(1))) unsigned long long *p;
+    __device__ __forceinline__ uint2 operator[](size_t i) const
+    {
+        const unsigned long long v = p[i];
+        return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+};
+
+// Minimum distance from each of the thread's first K candidates to the
+// l-mers of one string; the l-mer is the same for the whole wave.
 template <int K>
-__device__ __forceinline__ void scan_string(const PlaneRow yp, int L,
-                                            const uint2 (&c)[K],
-                                            uint32_t (&mind)[K], int d,
-                                            unsigned int live_mask)
+__device__ __forceinline__ void scan_string(const BRow yp, int L,
+                                            const uint2 *c, uint32_t *mind,
+                                            int d, unsigned int live_mask)
 {
     int j = 0;
     for (; j + 16 <= L; j += 16) {
@@ -203,9 +215,11 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         }
         __syncthreads();   // hc cleared
 
-        int nlive = kFBlock;   // upper bound; slots carry live bits
+        int nlive = (int)min<uint64_t>((uint64_t)kFBlock, total - f0);
         for (int si = 1; si < I.n && nlive > 0; si++) {
-            const PlaneRow yp = planes_row(I.planes, (size_t)si * L);
+            const BRow yp{(const __attribute__((address_space(1))) unsigned
+                           long long *)(const void *)(I.planes +
+                                                     (size_t)si * L)};
             uint32_t mind[kFPer];
 #pragma unroll
             for (int k = 0; k < kFPer; k++) {
@@ -213,8 +227,19 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
                 if ((live >> k) & 1u)
                     atomicAdd(&sh.hc[ref[k] - x_first], (uint32_t)L);
             }
-            if (__any(live != 0))
-                scan_string<kFPer>(yp, L, c, mind, d, live);
+            // after compaction the live candidates fill slots 0..kk-1: scan
+            // only those
+            const int kk = (nlive + kTPB - 1) / kTPB;
+            if (__any(live != 0)) {
+                if (kk <= 1)
+                    scan_string<1>(yp, L, c, mind, d, live);
+                else if (kk <= 2)
+                    scan_string<2>(yp, L, c, mind, d, live);
+                else if (kk <= 4)
+                    scan_string<4>(yp, L, c, mind, d, live);
+                else
+                    scan_string<kFPer>(yp, L, c, mind, d, live);
+            }
             unsigned int keep = 0, nk = 0;
 #pragma unroll
             for (int k = 0; k < kFPer; k++)

@@ -67,11 +67,14 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
     for (auto &ch : seqs)
         ch = "ACGT"[rng() & 3];
 
+    // tile suffixes around the default (more tiles vs longer tiles) and
+    // three survivor thresholds
     std::vector<std::pair<int, int>> cand;
-    const int s_hi = std::min(kMaxSuffix, l);
-    const int s_lo = std::max(kMinSuffix, std::max(l - 12, s_hi - 4));
+    const int s_def = default_suffix(l);
+    const int s_hi = std::min(std::min(kMaxSuffix, l), s_def + 2);
+    const int s_lo = std::max(kMinSuffix, std::max(l - kMaxTilePrefix, s_def - 2));
     for (int s = s_lo; s <= s_hi; s++)
-        for (int t : {32, 64, 128, 256})
+        for (int t : {32, 64, 128})
             cand.push_back({s, t});
 
     std::pair<int, int> saved;
