@@ -109,6 +109,8 @@ struct pms_ctx {
     hipGraph_t b_graph_def = nullptr;
     uint64_t b_graph_key = 0;
     uint64_t b_graph_replays = 0;
+    uint64_t b_heap_key = 0;      // shape of the last batch
+    uint64_t b_heap_need = 0;     // heap it needed (with slack)
 
     pms::Server *srv = nullptr;
 
