@@ -21,6 +21,29 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_OPS = 256 * 64 * 2.4e9     # int32 VALU lane ops/s (256 CU x 64 x 2.4 GHz)
 PEAK_HBM = 8.0e12                   # bytes/s
 
+# Algorithmic integer operations per unit of work (gfx950 forms):
+#  Hamming test on bit planes: v_xor + v_bitop3 (xor, or) + v_bcnt + half a
+#    v_min3 = 3.5
+#  tile prefix test: xor + bitop3 + and + bcnt, compare folded = 4
+#  word-level sphere mark: word index xor + the OR itself = 2
+OPS_TEST = 3.5
+OPS_PREFIX = 4.0
+OPS_MARK = 2.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pms_17_6_traffic.json")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch from the committed counter profile, if it was
+    taken on the current source of that kernel (else None)."""
+    try:
+        from paper_2403_00306_amd import profile_tools
+        rec = json.load(open(TRAFFIC_JSON))["kernels"][kernel]
+        if rec["source_sha"] == profile_tools.source_hash(kernel):
+            return rec["bytes"]
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -161,6 +184,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB: one device copy of this size at the end, to "
+                         "calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not "
@@ -213,23 +239,29 @@ def main():
 
     value = hcanon / (ms_step / 1000.0)
     k_ms = float(np.mean(kms))
-    # dominant kernel of the timed path: algorithmic integer work
+    # dominant kernel of the timed path (k_tiled): algorithmic integer work
+    # of one launch from its work counters, over its average HIP-event time
     L = m - l + 1
-    alg_ops = (stats["marks"] * 2 + stats["tile_passes"] * L * 5 +
-               stats["filter_tests"] * 4)
+    alg_ops = (stats["marks"] * OPS_MARK +
+               stats["tile_passes"] * L * OPS_PREFIX +
+               stats["filter_tests"] * OPS_TEST)
     achieved = alg_ops / (k_ms / 1000.0)
     roof = {"bound": "alu", "achieved": achieved / 1e12,
-            "peak": PEAK_ALU_OPS / 1e12, "unit": "Tops/s",
-            "frac": achieved / PEAK_ALU_OPS, "traffic": None,
+            "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved / PEAK_ALU_OPS,
+            "traffic": measured_traffic("k_tiled"),
             "kernel": "k_tiled", "kernel_ms": k_ms,
-            "ops_per_launch": alg_ops}
-    f_ops = hcanon * 3.5
+            "ops_per_launch": alg_ops, "marks": stats["marks"],
+            "prefix_tests": stats["tile_passes"] * L,
+            "filter_tests": stats["filter_tests"]}
+    f_ops = hcanon * OPS_TEST
     roof_filter = {"bound": "alu", "kernel": "k_filter",
                    "kernel_ms": fst["ms_main"],
                    "tests_per_s": hcanon / (fst["ms_main"] / 1000.0),
                    "achieved": f_ops / (fst["ms_main"] / 1000.0) / 1e12,
-                   "peak": PEAK_ALU_OPS / 1e12, "unit": "Tops/s",
-                   "frac": f_ops / (fst["ms_main"] / 1000.0) / PEAK_ALU_OPS}
+                   "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
+                   "frac": f_ops / (fst["ms_main"] / 1000.0) / PEAK_ALU_OPS,
+                   "traffic": measured_traffic("k_filter")}
     extra = {}
     if not args.no_extra:
         bctx = pms.Context(device=0, path=pms.PATH_BITSET)
@@ -238,12 +270,15 @@ def main():
         bst = bctx.stats()
         bcodes = d_out[:bcnt].cpu().numpy().view(np.uint64)
         assert np.array_equal(bcodes, motifs), "bitset path disagrees"
+        bw = bst["bytes_main"] / (bst["ms_main"] / 1000.0)
         extra["memory_heavy_bitset_path"] = {
             "solve_ms": bst["ms_total"], "kernel_ms": bst["ms_main"],
-            "bitset_bytes": 4 ** l // 8, "hbm_bytes": bst["bytes_main"],
-            "hbm_GBps": bst["bytes_main"] / (bst["ms_main"] / 1000.0) / 1e9,
-            "frac_hbm": bst["bytes_main"] / (bst["ms_main"] / 1000.0)
-            / PEAK_HBM}
+            "launches": bst["main_launches"], "bitset_bytes": 4 ** l // 8,
+            "roofline": {"bound": "hbm", "achieved": bw / 1e9,
+                         "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": bw / PEAK_HBM,
+                         "traffic": measured_traffic("k_bitset_pass"),
+                         "algorithmic_bytes": bst["bytes_main"]}}
         bctx.close()
     if not args.no_batch:
         log("batched")
@@ -274,6 +309,11 @@ def main():
            "roofline": roof, "roofline_filter": roof_filter,
            "cpu_baseline": cpu}
     rec.update(extra)
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
     print(json.dumps(rec), flush=True)
     fctx.close()
     ctx.close()
