@@ -35,7 +35,6 @@ constexpr int kYList = kYChunk + 4 * (kMaxL + 1);      // radius classes
 struct __align__(16) TileShared {
     unsigned long long U[kMaxWords];   // the string's union on this tile
     unsigned long long m3[256];        // word masks, copy of Tables::m3
-    uint16_t ball[kMaxWords];          // word-index XOR masks of table q
     union {
         uint32_t ylist[kYList];        // suffix codes of reaching l-mers
         uint64_t surv[kSurvMax];       // filter stage: codes left
@@ -46,7 +45,6 @@ struct __align__(16) TileShared {
     unsigned long long red64[kWaves];
     unsigned int red32[kWaves];
     unsigned long long bcast;
-    int ball_q;                        // which table sits in ball[]
     uint8_t hit[kSurvMax];             // filter stage: hit in this string
     uint8_t alive[kSurvMax];           // filter stage: still a candidate
 };
@@ -138,23 +136,6 @@ __device__ __forceinline__ void or_word(TileShared &sh, uint32_t w,
     atomicOr(&sh.U[wpos(w)], m);
 }
 
-// Bring ball table q into LDS (once per change of q). Call uniformly.
-__device__ __forceinline__ void load_ball(TileShared &sh, const Tables &tb,
-                                          int q)
-{
-    __syncthreads();
-    if (uni(sh.ball_q) == q)
-        return;
-    const uint16_t *src = tb.ball + tb.ball_base[q];
-    const int nq = 1 << (2 * q);
-    for (int i = threadIdx.x; i < nq; i += kTPB)
-        sh.ball[i] = src[i];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        sh.ball_q = q;
-    __syncthreads();
-}
-
 // OR into sh.U the union of the d-spheres of string `seq`'s l-mers,
 // restricted to the tile with prefix planes (Phi, Plo). The ball table of
 // q = s-3 must be in sh.ball. Ends with a barrier. Returns the number of
@@ -177,6 +158,10 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
     const g_u64 *yc = gptr(I.codes) + (size_t)seq * I.L;
     const uint32_t sufmask = (1u << (2 * s)) - 1u;
     const int *boff = tb.ball_off + q * 8;
+    // ball table q (read-only): each lane reads its entry once per class
+    const __attribute__((address_space(4))) uint16_t *ball =
+        (const __attribute__((address_space(4))) uint16_t *)(const void *)(
+            tb.ball + tb.ball_base[q]);
     unsigned long long marks = 0;
     for (int y0 = 0; y0 < I.L; y0 += kYChunk) {
         const int ny = min(kYChunk, I.L - y0);
@@ -230,7 +215,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 // every lane owns entries vt, vt+256, ...; the l-mer is
                 // the same for the whole wave (scalar registers)
                 for (uint32_t e = vt; e < bs; e += kTPB) {
-                    const uint32_t ent = sh.ball[e];
+                    const uint32_t ent = ball[e];
                     const uint32_t mask = ent & 0xfffu;
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
                     const unsigned long long *mt = sh.m3 + tt;
@@ -282,7 +267,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 const uint32_t slot = vt / bs;
                 const uint32_t e = vt - slot * bs;
                 if (slot < G) {
-                    const uint32_t ent = sh.ball[e];
+                    const uint32_t ent = ball[e];
                     const uint32_t mask = ent & 0xfffu;
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
                     const unsigned long long *mt = sh.m3 + tt;
@@ -387,9 +372,8 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     bool to_filter = false;
     for (si = 0; si < I.n; si++) {
         const int seq = uni(I.order[si]);
-        for (int w = tid; w < W; w += kTPB)
-            sh.U[w] = 0;
-        __syncthreads();
+        // U is all zero here: cleared at kernel start, by the previous
+        // pass's AND step, or after the previous tile's emission
         const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         unsigned long long cnt = 0;
@@ -397,7 +381,9 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         for (int k = 0; k < kWordsPerThread; k++) {
             const int w = tid + k * kTPB;
             if (w < W) {
-                const unsigned long long u = sh.U[wpos((uint32_t)w)];
+                const uint32_t pw = wpos((uint32_t)w);
+                const unsigned long long u = sh.U[pw];
+                sh.U[pw] = 0;
                 A[k] = (si == 0) ? u : (A[k] & u);
                 cnt += __popcll(A[k]);
             }
@@ -444,6 +430,9 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         const unsigned long long off = uni(sh.bcast);
         const bool fits = off + total <= heap_cap;
         emit_words(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
+        __syncthreads();
+        for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
+            sh.U[w] = 0;
         return;
     }
 
@@ -457,6 +446,8 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         sh.alive[tid] = tid < (int)total;
     }
     __syncthreads();
+    for (int w = tid; w < W; w += kTPB)       // U is zero for the next tile
+        sh.U[w] = 0;
     const int nsurv = (int)total;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int groups = (nsurv + 63) >> 6;                 // 1..4
@@ -528,7 +519,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         heap[off + pos] = sh.surv[tid];
 }
 
-__global__ __launch_bounds__(kTPB) void
+__global__ __launch_bounds__(kTPB, 4) void
 k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
         uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
 {
@@ -536,8 +527,8 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
     __shared__ int s_item;
     for (int i = threadIdx.x; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
-    if (threadIdx.x == 0)
-        sh.ball_q = -1;
+    for (int i = threadIdx.x; i < kMaxWords; i += kTPB)
+        sh.U[i] = 0;
     StatAcc acc = {0, 0, 0, 0};
     for (;;) {
         __syncthreads();
@@ -557,7 +548,6 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
             w.t1 = min(w.t0 + chunk, insts[0].ntiles);
         }
         const InstDev I = insts[w.inst];
-        load_ball(sh, tb, I.s - 3);
         for (uint64_t t = w.t0; t < w.t1; t++)
             run_tile(I, t, sh, tb, acc);
     }
@@ -592,7 +582,7 @@ int tiled_blocks_per_cu()
 
 // ---- memory-heavy bitset path ---------------------------------------------
 
-__global__ __launch_bounds__(kTPB) void
+__global__ __launch_bounds__(kTPB, 4) void
 k_bitset_pass(const InstDev *inst, int pass, Tables tb,
               unsigned long long *A, uint8_t *alive, TileStats *stats)
 {
@@ -605,9 +595,7 @@ k_bitset_pass(const InstDev *inst, int pass, Tables tb,
     const int seq = I.order[pass];
     for (int i = tid; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
-    if (tid == 0)
-        sh.ball_q = -1;
-    load_ball(sh, tb, q);
+
     unsigned long long marks = 0, passes = 0;
     for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
         if (pass > 0 && !alive[t])
