@@ -28,6 +28,7 @@ namespace pms {
 namespace {
 
 constexpr double kLaunchTargetMs = 2.0;
+constexpr int kMaxOrder = 4096;          // strings per request (serving)
 
 // First-fit sub-allocator over one device allocation (host bookkeeping).
 struct Pool {
@@ -167,8 +168,10 @@ int Server::start()
             hipSuccess ||
         hipHostMalloc((void **)&h_desc, sizeof(InstDev) * max_slots) !=
             hipSuccess ||
-        hipHostMalloc((void **)&h_small, 4096) != hipSuccess ||
-        hipHostMalloc((void **)&h_order, 4 * 65536) != hipSuccess)
+        hipHostMalloc((void **)&h_small, 8 * 3 * (size_t)max_slots + 64) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&h_order, 4 * kMaxOrder * (size_t)max_slots) !=
+            hipSuccess)
         return c->fail(PMS_EDEVICE, "serving pinned staging failed");
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -187,12 +190,16 @@ int Server::setup(Req *r)
                         r->surv_t, r->ntiles, r->heap_cap);
     InstDev *slot = d_slots + r->slot;
     memcpy(h_desc + r->slot, &r->desc, sizeof(InstDev));
+    int *ord = h_order + (size_t)kMaxOrder * r->slot;
     for (int i = 0; i < r->n; i++)
-        h_order[i] = i;
+        ord[i] = i;
+    // the slot's pinned staging is not reused before this request leaves,
+    // so the copies need no wait here; the request's seqs vector lives
+    // until release
     if (hipMemcpyAsync((void *)r->desc.seqs, r->seqs.data(),
                        (size_t)r->n * r->m, hipMemcpyHostToDevice, st) !=
             hipSuccess ||
-        hipMemcpyAsync((void *)r->desc.order, h_order, 4 * (size_t)r->n,
+        hipMemcpyAsync((void *)r->desc.order, ord, 4 * (size_t)r->n,
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(slot, h_desc + r->slot, sizeof(InstDev),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -200,9 +207,6 @@ int Server::setup(Req *r)
         launch_fill_u64(r->desc.heap_top, 1, 0, st) != hipSuccess ||
         launch_index(slot, 1, r->n * r->desc.wpr, r->n * r->desc.L, st) !=
             hipSuccess)
-        return PMS_EDEVICE;
-    // the pinned staging is reused by the next request: wait for the copies
-    if (hipStreamSynchronize(st) != hipSuccess)
         return PMS_EDEVICE;
     return PMS_OK;
 }
@@ -457,8 +461,8 @@ int pms_submit(pms_ctx *c, const pms_instance *in, uint64_t *ticket)
     if (rc)
         return c->fail(rc, "bad shape n=%d m=%d l=%d d=%d", in->n, in->m,
                        in->l, in->d);
-    if (in->n > 65536)
-        return c->fail(PMS_EINVAL, "serving: n=%d above 65536", in->n);
+    if (in->n > kMaxOrder)
+        return c->fail(PMS_EINVAL, "serving: n=%d above %d", in->n, kMaxOrder);
     Plan P = c->plan(in->n, in->m, in->l, in->d, PMS_PATH_TILED);
     if (P.path != PMS_PATH_TILED)
         return c->fail(PMS_EINVAL, "serving runs the tiled path, which does "
