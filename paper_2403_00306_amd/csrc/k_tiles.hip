@@ -122,18 +122,31 @@ __device__ __forceinline__ uint32_t wpos(uint32_t w)
     return w ^ ((w >> 5) & 31u) ^ ((w >> 10) & 31u);
 }
 
-// OR a single bit (bit b of tile word w) with a 32-bit atomic on the half
-// that holds it: one LDS bank per lane instead of two.
-__device__ __forceinline__ void or_bit(TileShared &sh, uint32_t w, uint32_t b)
+// wpos is linear over GF(2) (shifts, masks and XORs of bits), so
+// wpos(y ^ m) = wpos(y) ^ wpos(m): a lane keeps its XOR mask's part of the
+// LDS address, and an l-mer's part is computed once when it is listed.
+// A listed l-mer is a = (wpos(word index) << 6) | (last 3 bases); the byte
+// offset of its word is ((a >> 3) & ~7), of the 32-bit half that holds its
+// bit ((a >> 3) & ~3).
+__device__ __forceinline__ uint32_t list_entry(uint32_t ysuf)
 {
-    atomicOr(reinterpret_cast<unsigned int *>(sh.U) + 2u * wpos(w) + (b >> 5),
-             1u << (b & 31u));
+    return (wpos(ysuf >> 6) << 6) | (ysuf & 63u);
 }
 
-__device__ __forceinline__ void or_word(TileShared &sh, uint32_t w,
-                                        unsigned long long m)
+// OR a single bit with a 32-bit atomic on the half-word that holds it (one
+// LDS bank per lane instead of two). off = byte offset in sh.U.
+__device__ __forceinline__ void or32_at(TileShared &sh, uint32_t off,
+                                        uint32_t v)
 {
-    atomicOr(&sh.U[wpos(w)], m);
+    atomicOr(reinterpret_cast<unsigned int *>(
+                 reinterpret_cast<char *>(sh.U) + off), v);
+}
+
+__device__ __forceinline__ void or64_at(TileShared &sh, uint32_t off,
+                                        unsigned long long v)
+{
+    atomicOr(reinterpret_cast<unsigned long long *>(
+                 reinterpret_cast<char *>(sh.U) + off), v);
 }
 
 // OR into sh.U the union of the d-spheres of string `seq`'s l-mers,
@@ -143,10 +156,10 @@ __device__ __forceinline__ void or_word(TileShared &sh, uint32_t w,
 //
 // The reaching l-mers are grouped by radius r and every class is marked
 // entry-parallel: each lane keeps one XOR mask of the class's word-level
-// sphere in registers and walks the class's l-mers. When the sphere has at
-// least kTPB entries the whole group walks the same l-mer (read once by
-// broadcast into scalar registers); a smaller sphere is repeated in
-// 256/bs lane groups that walk different l-mers.
+// sphere in registers and walks the class's l-mers. When the sphere has
+// more than kTPB/2 entries every wave walks the same l-mers (64 read at
+// once, then broadcast into scalar registers by readlane); a smaller
+// sphere is repeated in 256/bs lane groups that walk different l-mers.
 __device__ unsigned long long mark_string(const InstDev &I, int seq,
                                           uint32_t Phi, uint32_t Plo,
                                           uint32_t premask, TileShared &sh,
@@ -179,7 +192,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
                 if (k <= d) {
                     rr[u] = d - k;
-                    ys[u] = (uint32_t)yc[y0 + j] & sufmask;
+                    ys[u] = list_entry((uint32_t)yc[y0 + j] & sufmask);
                     atomicAdd(&sh.rcnt[d - k], 1);
                 }
             }
@@ -200,6 +213,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
             if (rr[u] >= 0)
                 sh.ylist[atomicAdd(&sh.rpos[rr[u]], 1)] = ys[u];
         __syncthreads();
+        const uint32_t lane = (uint32_t)tid & 63u;
         for (int r = 0; r <= d; r++) {
             const int c = uni(sh.rcnt[r]);
             if (c == 0)
@@ -210,91 +224,114 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
             marks += (unsigned long long)c * bs;
             // rotate the lane assignment per class so that the lanes a
             // class leaves idle fall in a different wave each time
-            const uint32_t vt = (uint32_t)(tid + 64 * r) & (uint32_t)(kTPB - 1);
-            if (bs >= (uint32_t)kTPB) {
-                // every lane owns entries vt, vt+256, ...; the l-mer is
-                // the same for the whole wave (scalar registers)
-                for (uint32_t e = vt; e < bs; e += kTPB) {
-                    const uint32_t ent = ball[e];
-                    const uint32_t mask = ent & 0xfffu;
-                    const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
-                    const unsigned long long *mt = sh.m3 + tt;
-                    int yi = 0;
-                    if (__ballot(tt != 0) == 0) {
-                        // the whole wave has in-word radius 0: the word mask
-                        // is the single bit of the l-mer's last 3 bases
-                        for (; yi + 4 <= c; yi += 4) {
-                            const uint4 y4 = *(const uint4 *)(yl + yi);
-                            const uint32_t a0 = __builtin_amdgcn_readfirstlane(y4.x);
-                            const uint32_t a1 = __builtin_amdgcn_readfirstlane(y4.y);
-                            const uint32_t a2 = __builtin_amdgcn_readfirstlane(y4.z);
-                            const uint32_t a3 = __builtin_amdgcn_readfirstlane(y4.w);
-                            or_bit(sh, (a0 >> 6) ^ mask, a0 & 63u);
-                            or_bit(sh, (a1 >> 6) ^ mask, a1 & 63u);
-                            or_bit(sh, (a2 >> 6) ^ mask, a2 & 63u);
-                            or_bit(sh, (a3 >> 6) ^ mask, a3 & 63u);
-                        }
-                        for (; yi < c; yi++) {
-                            const uint32_t y = __builtin_amdgcn_readfirstlane(yl[yi]);
-                            or_bit(sh, (y >> 6) ^ mask, y & 63u);
-                        }
+            const uint32_t rot = 64u * (uint32_t)r;
+            if (bs > (uint32_t)kTPB / 2) {
+                // Entry-parallel: lane owns entries e, e+256, ... of the
+                // sphere and the wave walks the class's l-mers, 64 at a
+                // time: one LDS read per lane, then broadcast by readlane.
+                // Every lane of a working wave stays active (readlane needs
+                // the source lane's value): a lane past the end of the
+                // sphere repeats an entry that another wave, or itself in
+                // the previous round, already ORs; ORs are idempotent.
+                const uint32_t wfirst =
+                    uni(((uint32_t)tid - lane + rot) & (uint32_t)(kTPB - 1));
+                for (uint32_t eb = 0; eb < bs; eb += kTPB) {
+                    const uint32_t e0 = wfirst + eb;
+                    if (e0 >= bs)
                         continue;
-                    }
-                    for (; yi + 4 <= c; yi += 4) {
-                        const uint4 y4 = *(const uint4 *)(yl + yi);
-                        const uint32_t a0 = __builtin_amdgcn_readfirstlane(y4.x);
-                        const uint32_t a1 = __builtin_amdgcn_readfirstlane(y4.y);
-                        const uint32_t a2 = __builtin_amdgcn_readfirstlane(y4.z);
-                        const uint32_t a3 = __builtin_amdgcn_readfirstlane(y4.w);
-                        const unsigned long long m0 = mt[(a0 & 63u) * 4u];
-                        const unsigned long long m1 = mt[(a1 & 63u) * 4u];
-                        const unsigned long long m2 = mt[(a2 & 63u) * 4u];
-                        const unsigned long long m3v = mt[(a3 & 63u) * 4u];
-                        or_word(sh, (a0 >> 6) ^ mask, m0);
-                        or_word(sh, (a1 >> 6) ^ mask, m1);
-                        or_word(sh, (a2 >> 6) ^ mask, m2);
-                        or_word(sh, (a3 >> 6) ^ mask, m3v);
-                    }
-                    for (; yi < c; yi++) {
-                        const uint32_t y = __builtin_amdgcn_readfirstlane(yl[yi]);
-                        or_word(sh, (y >> 6) ^ mask, mt[(y & 63u) * 4u]);
+                    uint32_t e = e0 + lane;
+                    e = e < bs ? e : e - (eb ? (uint32_t)kTPB : bs);
+                    const uint32_t ent = ball[e];
+                    const uint32_t lc = 8u * wpos(ent & 0xfffu);
+                    const int tt = min(r - (int)(ent >> 12), 3);
+                    const unsigned long long *mt = sh.m3 + tt;
+                    const bool single = __ballot(tt != 0) == 0;
+                    for (int y0c = 0; y0c < c; y0c += 64) {
+                        const int nc = min(64, c - y0c);
+                        const int vl =
+                            (int)yl[y0c + min((int)lane, nc - 1)];
+                        // a VALU copy: the LDS read is waited for here,
+                        // once, and not at every readlane below (where a
+                        // wait would also drain this wave's pending ORs)
+                        int v;
+                        asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"(vl));
+                        int j = 0;
+                        if (single) {
+                            // in-word radius 0 in the whole wave: the word
+                            // mask is the single bit of the last 3 bases
+                            for (; j + 4 <= nc; j += 4) {
+                                const uint32_t a0 = __builtin_amdgcn_readlane(v, j);
+                                const uint32_t a1 = __builtin_amdgcn_readlane(v, j + 1);
+                                const uint32_t a2 = __builtin_amdgcn_readlane(v, j + 2);
+                                const uint32_t a3 = __builtin_amdgcn_readlane(v, j + 3);
+                                or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
+                                or32_at(sh, ((a1 >> 3) & ~3u) ^ lc, 1u << (a1 & 31u));
+                                or32_at(sh, ((a2 >> 3) & ~3u) ^ lc, 1u << (a2 & 31u));
+                                or32_at(sh, ((a3 >> 3) & ~3u) ^ lc, 1u << (a3 & 31u));
+                            }
+                            for (; j < nc; j++) {
+                                const uint32_t a0 = __builtin_amdgcn_readlane(v, j);
+                                or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
+                            }
+                        } else {
+                            for (; j + 4 <= nc; j += 4) {
+                                const uint32_t a0 = __builtin_amdgcn_readlane(v, j);
+                                const uint32_t a1 = __builtin_amdgcn_readlane(v, j + 1);
+                                const uint32_t a2 = __builtin_amdgcn_readlane(v, j + 2);
+                                const uint32_t a3 = __builtin_amdgcn_readlane(v, j + 3);
+                                const unsigned long long m0 = mt[(a0 & 63u) * 4u];
+                                const unsigned long long m1 = mt[(a1 & 63u) * 4u];
+                                const unsigned long long m2 = mt[(a2 & 63u) * 4u];
+                                const unsigned long long m3v = mt[(a3 & 63u) * 4u];
+                                or64_at(sh, ((a0 >> 3) & ~7u) ^ lc, m0);
+                                or64_at(sh, ((a1 >> 3) & ~7u) ^ lc, m1);
+                                or64_at(sh, ((a2 >> 3) & ~7u) ^ lc, m2);
+                                or64_at(sh, ((a3 >> 3) & ~7u) ^ lc, m3v);
+                            }
+                            for (; j < nc; j++) {
+                                const uint32_t a0 = __builtin_amdgcn_readlane(v, j);
+                                or64_at(sh, ((a0 >> 3) & ~7u) ^ lc,
+                                        mt[(a0 & 63u) * 4u]);
+                            }
+                        }
                     }
                 }
             } else {
                 // G = 256/bs groups of bs lanes: each lane owns one entry
                 // and its group walks every G-th l-mer of the class
+                const uint32_t vt = ((uint32_t)tid + rot) & (uint32_t)(kTPB - 1);
                 const uint32_t G = (uint32_t)kTPB / bs;
                 const uint32_t slot = vt / bs;
                 const uint32_t e = vt - slot * bs;
                 if (slot < G) {
                     const uint32_t ent = ball[e];
-                    const uint32_t mask = ent & 0xfffu;
+                    const uint32_t lc = 8u * wpos(ent & 0xfffu);
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
                     const unsigned long long *mt = sh.m3 + tt;
                     uint32_t yi = slot;
                     if (__ballot(tt != 0) == 0) {
                         // in-word radius 0 in every active lane: single bit
                         for (; yi + G < (uint32_t)c; yi += 2 * G) {
-                            const uint32_t y0 = yl[yi], y1 = yl[yi + G];
-                            or_bit(sh, (y0 >> 6) ^ mask, y0 & 63u);
-                            or_bit(sh, (y1 >> 6) ^ mask, y1 & 63u);
+                            const uint32_t a0 = yl[yi], a1 = yl[yi + G];
+                            or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
+                            or32_at(sh, ((a1 >> 3) & ~3u) ^ lc, 1u << (a1 & 31u));
                         }
                         if (yi < (uint32_t)c) {
-                            const uint32_t y = yl[yi];
-                            or_bit(sh, (y >> 6) ^ mask, y & 63u);
+                            const uint32_t a0 = yl[yi];
+                            or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
                         }
                         continue;
                     }
                     for (; yi + G < (uint32_t)c; yi += 2 * G) {
-                        const uint32_t y0 = yl[yi], y1 = yl[yi + G];
-                        const unsigned long long m0 = mt[(y0 & 63u) * 4u];
-                        const unsigned long long m1 = mt[(y1 & 63u) * 4u];
-                        or_word(sh, (y0 >> 6) ^ mask, m0);
-                        or_word(sh, (y1 >> 6) ^ mask, m1);
+                        const uint32_t a0 = yl[yi], a1 = yl[yi + G];
+                        const unsigned long long m0 = mt[(a0 & 63u) * 4u];
+                        const unsigned long long m1 = mt[(a1 & 63u) * 4u];
+                        or64_at(sh, ((a0 >> 3) & ~7u) ^ lc, m0);
+                        or64_at(sh, ((a1 >> 3) & ~7u) ^ lc, m1);
                     }
                     if (yi < (uint32_t)c) {
-                        const uint32_t y = yl[yi];
-                        or_word(sh, (y >> 6) ^ mask, mt[(y & 63u) * 4u]);
+                        const uint32_t a0 = yl[yi];
+                        or64_at(sh, ((a0 >> 3) & ~7u) ^ lc, mt[(a0 & 63u) * 4u]);
                     }
                 }
             }
