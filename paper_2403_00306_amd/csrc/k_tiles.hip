@@ -45,9 +45,12 @@ struct __align__(16) TileShared {
     unsigned long long red64[kWaves];
     unsigned int red32[kWaves];
     unsigned long long bcast;
-    uint8_t hit[kSurvMax];             // filter stage: hit in this string
-    uint8_t alive[kSurvMax];           // filter stage: still a candidate
 };
+
+// the filter stage keeps two plane buffers, a code buffer and a chunk of
+// the current string's l-mer planes in sh.U
+constexpr int kFiltChunk = kMaxWords - 3 * kSurvMax;
+static_assert(kFiltChunk >= kTPB, "filter scratch exceeds the tile");
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 {
@@ -474,86 +477,111 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     }
 
     // ---- filter stage: test the few codes left against the rest --------
-    // Survivors are dealt to the waves in groups of 64 (one per lane); when
-    // there are fewer groups than waves, each group's l-mer range is split
-    // across several waves and their hits are ORed in LDS.
+    // The live codes are kept compacted, in code order, with their bit
+    // planes. For each remaining string every code gets G lanes (G = 256/N
+    // rounded down to a power of two, at most one wave) that split the
+    // string's l-mers; a group stops as soon as one of its lanes finds an
+    // l-mer within distance d, and the codes without such an l-mer drop
+    // out before the next string. Codes and planes are double-buffered in
+    // the tile's LDS words, which are free during this stage.
     emit_words(sh, W, t, s, sh.surv, true, sh.red32);
-    if (tid < kSurvMax) {
-        sh.hit[tid] = 0;
-        sh.alive[tid] = tid < (int)total;
+    __syncthreads();
+    int N = (int)total;
+    uint2 mypl = make_uint2(0, 0);
+    if (tid < N) {
+        const uint64_t code = sh.surv[tid];
+        sh.U[(code >> 6) & (uint64_t)(W - 1)] = 0;   // the word A left there
+        mypl = code_planes(code, I.l);
     }
     __syncthreads();
-    for (int w = tid; w < W; w += kTPB)       // U is zero for the next tile
-        sh.U[w] = 0;
-    const int nsurv = (int)total;
-    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int groups = (nsurv + 63) >> 6;                 // 1..4
-    const int parts = kWaves / groups;                    // y-range splits
-    const int grp = wid % groups, part = wid / groups;
-    const int si_ = grp * 64 + lane;                      // my survivor
-    const bool mine_slot = part < parts && si_ < nsurv;
-    uint2 cp = make_uint2(0, 0);
-    if (mine_slot)
-        cp = code_planes(sh.surv[si_], I.l);
-    bool alive = tid < nsurv;                              // survivor tid
-    for (int sj = si + 1; sj < I.n; sj++) {
-        const int nalive = uni(__syncthreads_count(alive));
-        if (nalive == 0)
-            break;
+    uint2 *const plb0 = reinterpret_cast<uint2 *>(sh.U);
+    uint2 *const plb1 = plb0 + kSurvMax;
+    uint64_t *const cdb1 = reinterpret_cast<uint64_t *>(sh.U) + 2 * kSurvMax;
+    if (tid < N)
+        plb0[tid] = mypl;
+    __syncthreads();
+    uint2 *const ysh = reinterpret_cast<uint2 *>(sh.U) + 3 * kSurvMax;
+    const int lane = tid & 63;
+    const int L = I.L;
+    int cur = 0;
+    for (int sj = si + 1; sj < I.n && N > 0; sj++) {
         if (tid == 0)
-            acc.ftests += (unsigned long long)nalive * (unsigned long long)I.L;
-        const bool mine = mine_slot && sh.alive[si_];
-        if (__ballot(mine) != 0) {
-            const PlaneRow yp = planes_row(I.planes,
-                                           (size_t)uni(I.order[sj]) * I.L);
-            const int j0 = (I.L * part) / parts;
-            const int j1 = (I.L * (part + 1)) / parts;
-            uint32_t mind = 255;
-            int j = j0;
-            for (; j + 32 <= j1; j += 32) {
+            acc.ftests += (unsigned long long)N * (unsigned long long)L;
+        int lg = 6;
+        while (lg > 0 && (N << lg) > kTPB)
+            lg--;
+        const int G = 1 << lg;
+        const int ci = tid >> lg, sub = tid & (G - 1);
+        const unsigned long long gmask =
+            (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+        const int gbase = lane & ~(G - 1);
+        const uint2 *plc = cur ? plb1 : plb0;
+        const uint64_t *cdc = cur ? cdb1 : sh.surv;
+        const uint2 *yrow = reinterpret_cast<const uint2 *>(I.planes) +
+                            (size_t)uni(I.order[sj]) * (size_t)L;
+        const uint2 cp = (ci < N) ? plc[ci] : make_uint2(0, 0);
+        uint32_t mind = 255;
+        bool found = false;                 // my group has a hit
+        for (int c0 = 0; c0 < L; c0 += kFiltChunk) {
+            // the string's planes, one chunk at a time, into LDS
+            const int len = min(kFiltChunk, L - c0);
+            for (int j = tid; j < len; j += kTPB)
+                ysh[j] = yrow[c0 + j];
+            __syncthreads();
+            if (ci < N && !found) {
+                // indexes past the end repeat the chunk's last l-mer
+                for (int j = sub;;) {
+                    uint32_t h = 255;
 #pragma unroll
-                for (int u = 0; u < 32; u += 2) {
-                    const uint2 y0 = yp[j + u], y1 = yp[j + u + 1];
-                    const uint32_t h0 = __popc((cp.x ^ y0.x) | (cp.y ^ y0.y));
-                    const uint32_t h1 = __popc((cp.x ^ y1.x) | (cp.y ^ y1.y));
-                    mind = min(mind, min(h0, h1));
-                }
-                if (__all(!mine || mind <= (uint32_t)I.d))
-                    break;
-            }
-            if (j + 32 > j1) {
-                for (; j < j1; j++) {
-                    const uint2 y = yp[j];
-                    mind = min(mind, (uint32_t)__popc((cp.x ^ y.x) |
-                                                      (cp.y ^ y.y)));
+                    for (int u = 0; u < 8; u++) {
+                        const uint2 y = ysh[min(j + u * G, len - 1)];
+                        h = min(h, (uint32_t)__popc((cp.x ^ y.x) | (cp.y ^ y.y)));
+                    }
+                    mind = min(mind, h);
+                    j += 8 * G;
+                    const unsigned long long hb = __ballot(mind <= (uint32_t)I.d);
+                    if (j >= len || ((hb >> gbase) & gmask) != 0)
+                        break;
                 }
             }
-            if (mine && mind <= (uint32_t)I.d)
-                sh.hit[si_] = 1;
+            found = ((__ballot(mind <= (uint32_t)I.d) >> gbase) & gmask) != 0;
+            // (a barrier either way: the next chunk or string rewrites ysh)
+            if (c0 + kFiltChunk >= L)
+                __syncthreads();
+            else if (__syncthreads_count(ci < N && !found) == 0)
+                break;
+        }
+        const unsigned long long hb = __ballot(mind <= (uint32_t)I.d);
+        const bool keep = sub == 0 && ci < N && ((hb >> gbase) & gmask) != 0;
+        unsigned int nkeep;
+        const unsigned int pos = block_exscan(keep ? 1u : 0u, sh.red32, &nkeep);
+        if (keep) {
+            (cur ? plb0 : plb1)[pos] = plc[ci];
+            (cur ? sh.surv : cdb1)[pos] = cdc[ci];
         }
         __syncthreads();
-        if (tid < nsurv) {
-            alive = alive && sh.hit[tid];
-            sh.hit[tid] = 0;
-        }
-        if (tid < kSurvMax)
-            sh.alive[tid] = alive;
+        cur ^= 1;
+        N = (int)nkeep;
     }
-    // ordered compaction of the survivors into the heap
-    unsigned int ntot;
-    const unsigned int pos = block_exscan(alive ? 1u : 0u, sh.red32, &ntot);
+    // the survivors, in code order, into the heap
+    const uint64_t *cdc = cur ? cdb1 : sh.surv;
     if (tid == 0) {
         unsigned long long off = 0;
-        if (ntot)
-            off = atomicAdd(heap_top, (unsigned long long)ntot);
+        if (N)
+            off = atomicAdd(heap_top, (unsigned long long)N);
         sh.bcast = off;
-        tile_cnt[g] = ntot;
+        tile_cnt[g] = (uint32_t)N;
         tile_heap_off[g] = off;
     }
     __syncthreads();
     const unsigned long long off = sh.bcast;
-    if (alive && off + ntot <= heap_cap)
-        heap[off + pos] = sh.surv[tid];
+    if (tid < N && off + (unsigned long long)N <= heap_cap)
+        heap[off + tid] = cdc[tid];
+    __syncthreads();
+    // clear the scratch words for the next tile
+    const int used = 3 * kSurvMax + min(L, kFiltChunk);
+    for (int w = tid; w < used; w += kTPB)
+        sh.U[w] = 0;
 }
 
 __global__ __launch_bounds__(kTPB, 4) void
