@@ -262,7 +262,7 @@ std::pair<int, int> pms_ctx::tile_config(int n, int m, int l, int d)
     auto t = tune.find(tune_key(l, d, n, m));
     if (t != tune.end())
         return t->second;
-    return {default_suffix(l), 128};
+    return {default_suffix(l), kDefaultSurv};
 }
 
 Plan pms_ctx::plan(int n, int m, int l, int d, int forced)

@@ -16,6 +16,7 @@ constexpr int kMaxWords = 1 << (2 * (kMaxSuffix - 3));
 constexpr int kWordsPerThread = kMaxWords / kTPB;   // 16
 constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
+constexpr int kDefaultSurv = 64;   // default threshold to enter it
 constexpr int kBallDigits = kMaxSuffix - 3;         // 6 word-index digits
 
 // Read-only views of device arrays held in descriptors. The l-mer tables

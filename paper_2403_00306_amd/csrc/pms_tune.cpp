@@ -74,7 +74,7 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
     const int s_hi = std::min(std::min(kMaxSuffix, l), s_def + 2);
     const int s_lo = std::max(kMinSuffix, std::max(l - kMaxTilePrefix, s_def - 2));
     for (int s = s_lo; s <= s_hi; s++)
-        for (int t : {32, 64, 128})
+        for (int t : {32, 64, 96})
             cand.push_back({s, t});
 
     std::pair<int, int> saved;
