@@ -51,6 +51,16 @@ def _load():
             ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
             ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p),
             ctypes.POINTER(ctypes.c_size_t)]
+        for fn in (lib.oracle_q1, lib.oracle_q0):
+            fn.restype = ctypes.c_int
+            fn.argtypes = [
+                ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                ctypes.POINTER(u64p), ctypes.POINTER(ctypes.c_size_t)]
+        lib.oracle_hit_count.restype = ctypes.c_int
+        lib.oracle_hit_count.argtypes = [
+            ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_uint64]
         lib.oracle_is_motif.restype = ctypes.c_int
         lib.oracle_is_motif.argtypes = [
             ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -138,6 +148,39 @@ def o0(seqs, n, m, l, d, threads=0) -> np.ndarray:
     if rc != OR_OK:
         raise OracleError(rc, "oracle_o0")
     return _take(out, count.value)
+
+
+def _quorum(fn, name, seqs, n, m, l, d, q, threads):
+    buf = _seq_bytes(seqs)
+    assert len(buf) == n * m
+    out = ctypes.POINTER(ctypes.c_uint64)()
+    count = ctypes.c_size_t(0)
+    rc = fn(buf, n, m, l, d, q, threads, ctypes.byref(out),
+            ctypes.byref(count))
+    if rc != OR_OK:
+        raise OracleError(rc, name)
+    return _take(out, count.value)
+
+
+def q1(seqs, n, m, l, d, q, threads=0) -> np.ndarray:
+    """(l,d,q)-motifs from the spheres of the l-mers of s_1..s_{n-q+1}
+    (Observation 3.1)."""
+    return _quorum(_load().oracle_q1, "oracle_q1", seqs, n, m, l, d, q,
+                   threads)
+
+
+def q0(seqs, n, m, l, d, q, threads=0) -> np.ndarray:
+    """(l,d,q)-motifs by brute force over all 4^l codes."""
+    return _quorum(_load().oracle_q0, "oracle_q0", seqs, n, m, l, d, q,
+                   threads)
+
+
+def hit_count(seqs, n, m, l, d, code) -> int:
+    """Number of strings with an l-mer within distance d of the code."""
+    rc = _load().oracle_hit_count(_seq_bytes(seqs), n, m, l, d, int(code))
+    if rc < 0:
+        raise OracleError(rc, "oracle_hit_count")
+    return rc
 
 
 def is_motif(seqs, n, m, l, d, code) -> bool:

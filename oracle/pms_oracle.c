@@ -33,6 +33,17 @@
  *   O0 (pattern-driven, Sec. 1.3.1): try every one of the 4^l l-mers and
  *      compare it character by character with every l-mer of every string.
  *
+ * Quorum (the qPMS definition with q <= n, Definition 5): M is an
+ * (l,d,q)-motif when at least q of the n strings have an l-mer within
+ * distance d of it. Two more independent ways to get that set:
+ *   Q1 (Observation 3.1): the first string in which a motif has a
+ *      d-neighbour is one of s_1..s_{n-q+1}, so every motif lies in B(x,d)
+ *      for some l-mer x of one of those strings; enumerate those spheres and
+ *      keep the candidates with a d-neighbour in at least q strings.
+ *   Q0 (pattern-driven): every one of the 4^l l-mers, compared character by
+ *      character with every l-mer of every string, kept when at least q
+ *      strings have a d-neighbour.
+ *
  * O1 also counts the canonical number of Hamming tests, H_canon: for each
  * enumerated candidate (with multiplicity over references x), (m-l+1) times
  * the number of strings s_2..s_n examined, up to and including the first one
@@ -551,6 +562,281 @@ int oracle_is_motif(const char *seqs, int n, int m, int l, int d,
             return 0;
     }
     return 1;
+}
+
+/* ---- quorum: (l,d,q)-motifs ------------------------------------------- */
+
+static int check_q(int n, int m, int l, int d, int q)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    return (q < 1 || q > n) ? OR_EINVAL : OR_OK;
+}
+
+/* Number of strings with an l-mer within distance d of the packed code,
+ * counted until the answer is settled: returns q as soon as q strings have
+ * one, and stops early when too few strings are left to reach q. */
+static int q_hits(const uint64_t *codes, int n, int L, int d, int q,
+                  uint64_t cand)
+{
+    int hits = 0;
+    for (int i = 0; i < n; i++) {
+        if (hits + (n - i) < q)
+            break;
+        const uint64_t *row = codes + (size_t)i * L;
+        for (int j = 0; j < L; j++)
+            if (hamming_packed(cand, row[j]) <= d) {
+                hits++;
+                break;
+            }
+        if (hits >= q)
+            break;
+    }
+    return hits;
+}
+
+typedef struct {
+    const uint64_t *codes;
+    const unsigned char *bases;
+    int n, m, L, l, d, q, nthreads, tid;
+    vec64 out;
+} q1_job;
+
+/* T_d(x) as in O1: every element of B(x,d) once. */
+static void q1_ball(q1_job *J, const unsigned char *x, uint64_t cand,
+                    int from, int budget)
+{
+    if (q_hits(J->codes, J->n, J->L, J->d, J->q, cand) >= J->q)
+        vpush(&J->out, cand);
+    if (budget == 0)
+        return;
+    for (int p = from; p < J->l; p++) {
+        int shift = 2 * (J->l - 1 - p);
+        for (int b = 0; b < 4; b++) {
+            if (b == x[p])
+                continue;
+            q1_ball(J, x, cand ^ ((uint64_t)(x[p] ^ b) << shift), p + 1,
+                    budget - 1);
+        }
+    }
+}
+
+static void *q1_worker(void *arg)
+{
+    q1_job *J = (q1_job *)arg;
+    /* references: every l-mer of s_1..s_{n-q+1}, split evenly */
+    long long nref = (long long)(J->n - J->q + 1) * J->L;
+    long long lo = nref * J->tid / J->nthreads;
+    long long hi = nref * (J->tid + 1) / J->nthreads;
+    for (long long r = lo; r < hi; r++) {
+        int i = (int)(r / J->L), j = (int)(r % J->L);
+        const unsigned char *x = J->bases + (size_t)i * J->m + j;
+        q1_ball(J, x, lmer_code(x, J->l), 0, J->d);
+    }
+    return NULL;
+}
+
+/* Concatenate the per-thread vectors; sort and drop repeats if asked. */
+static int gather_out(vec64 *v, int T, int dedup, uint64_t **out,
+                      size_t *count)
+{
+    size_t tot = 0;
+    int oom = 0;
+    for (int t = 0; t < T; t++) {
+        tot += v[t].n;
+        oom |= v[t].oom;
+    }
+    uint64_t *res = (uint64_t *)malloc(sizeof(uint64_t) * (tot ? tot : 1));
+    if (!res || oom) {
+        free(res);
+        return OR_ENOMEM;
+    }
+    size_t w = 0;
+    for (int t = 0; t < T; t++) {
+        if (v[t].n)
+            memcpy(res + w, v[t].v, v[t].n * sizeof(uint64_t));
+        w += v[t].n;
+    }
+    *count = dedup ? sort_unique(res, tot) : tot;
+    *out = res;
+    return OR_OK;
+}
+
+/* Q1: the (l,d,q)-motifs by Observation 3.1 (see the file header). */
+int oracle_q1(const char *seqs, int n, int m, int l, int d, int q,
+              int nthreads, uint64_t **out, size_t *count)
+{
+    int rc = check_q(n, m, l, d, q);
+    if (rc)
+        return rc;
+    int L = m - l + 1;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * L);
+    int T = pick_threads(nthreads);
+    q1_job *jobs = (q1_job *)calloc((size_t)T, sizeof(q1_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    vec64 *vs = (vec64 *)calloc((size_t)T, sizeof(vec64));
+    if (!bases || !codes || !jobs || !th || !vs) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    if (decode(seqs, total, bases) >= 0) {
+        rc = OR_EBASE;
+        goto done;
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < L; j++)
+            codes[(size_t)i * L + j] = lmer_code(bases + (size_t)i * m + j, l);
+    for (int t = 0; t < T; t++) {
+        q1_job *J = &jobs[t];
+        J->codes = codes;
+        J->bases = bases;
+        J->n = n;
+        J->m = m;
+        J->L = L;
+        J->l = l;
+        J->d = d;
+        J->q = q;
+        J->nthreads = T;
+        J->tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, q1_worker, &jobs[t]);
+    q1_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    for (int t = 0; t < T; t++)
+        vs[t] = jobs[t].out;
+    rc = gather_out(vs, T, 1, out, count);
+done:
+    if (jobs)
+        for (int t = 0; t < T; t++)
+            free(jobs[t].out.v);
+    free(vs);
+    free(jobs);
+    free(th);
+    free(bases);
+    free(codes);
+    return rc;
+}
+
+typedef struct {
+    const unsigned char *bases;
+    int n, m, l, d, q, nthreads, tid;
+    vec64 out;
+} q0_job;
+
+static void *q0_worker(void *arg)
+{
+    q0_job *J = (q0_job *)arg;
+    uint64_t space = 1ULL << (2 * J->l);
+    uint64_t lo = (uint64_t)((__uint128_t)space * J->tid / J->nthreads);
+    uint64_t hi = (uint64_t)((__uint128_t)space * (J->tid + 1) / J->nthreads);
+    unsigned char M[32];
+    for (uint64_t c = lo; c < hi; c++) {
+        for (int j = 0; j < J->l; j++)
+            M[j] = (unsigned char)((c >> (2 * (J->l - 1 - j))) & 3);
+        /* Definitions 4 and 5: count the strings with an l-mer within d */
+        int hits = 0;
+        for (int i = 0; i < J->n; i++) {
+            const unsigned char *s = J->bases + (size_t)i * J->m;
+            int ok = 0;
+            for (int j = 0; j + J->l <= J->m && !ok; j++)
+                ok = hamming_naive(M, s + j, J->l) <= J->d;
+            hits += ok;
+        }
+        if (hits >= J->q)
+            vpush(&J->out, c);
+    }
+    return NULL;
+}
+
+/* Q0: brute force over all 4^l codes (small l only). */
+int oracle_q0(const char *seqs, int n, int m, int l, int d, int q,
+              int nthreads, uint64_t **out, size_t *count)
+{
+    int rc = check_q(n, m, l, d, q);
+    if (rc)
+        return rc;
+    if (l > 16)
+        return OR_EINVAL;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    int T = pick_threads(nthreads);
+    q0_job *jobs = (q0_job *)calloc((size_t)T, sizeof(q0_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    vec64 *vs = (vec64 *)calloc((size_t)T, sizeof(vec64));
+    if (!bases || !jobs || !th || !vs) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    if (decode(seqs, total, bases) >= 0) {
+        rc = OR_EBASE;
+        goto done;
+    }
+    for (int t = 0; t < T; t++) {
+        jobs[t].bases = bases;
+        jobs[t].n = n;
+        jobs[t].m = m;
+        jobs[t].l = l;
+        jobs[t].d = d;
+        jobs[t].q = q;
+        jobs[t].nthreads = T;
+        jobs[t].tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, q0_worker, &jobs[t]);
+    q0_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    for (int t = 0; t < T; t++)
+        vs[t] = jobs[t].out;
+    /* ascending code ranges per thread: already sorted, no repeats */
+    rc = gather_out(vs, T, 0, out, count);
+done:
+    if (jobs)
+        for (int t = 0; t < T; t++)
+            free(jobs[t].out.v);
+    free(vs);
+    free(jobs);
+    free(th);
+    free(bases);
+    return rc;
+}
+
+/* Number of strings that have an l-mer within distance d of the code
+ * (Definitions 4-5, character by character): spot checks of quorum
+ * outputs too large to recompute whole. Negative = error. */
+int oracle_hit_count(const char *seqs, int n, int m, int l, int d,
+                     uint64_t code)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    if (l < 32 && (code >> (2 * l)) != 0)
+        return OR_EINVAL;
+    unsigned char M[32];
+    for (int j = 0; j < l; j++)
+        M[j] = (unsigned char)((code >> (2 * (l - 1 - j))) & 3);
+    int hits = 0;
+    for (int i = 0; i < n; i++) {
+        const char *s = seqs + (size_t)i * m;
+        int ok = 0;
+        for (int j = 0; j + l <= m && !ok; j++) {
+            int h = 0;
+            for (int k = 0; k < l; k++) {
+                int b = base_code((unsigned char)s[j + k]);
+                if (b < 0)
+                    return OR_EBASE;
+                h += (b != M[k]);
+            }
+            ok = h <= d;
+        }
+        hits += ok;
+    }
+    return hits;
 }
 
 void oracle_free(void *p)

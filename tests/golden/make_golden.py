@@ -3,6 +3,7 @@
 Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
 on inputs from the seeded generator; nothing here touches the GPU library.
 Run from the repository root:  python tests/golden/make_golden.py
+(add "quorum" to write only the quorum files)
 """
 import hashlib
 import os
@@ -17,6 +18,9 @@ import pmsgen  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CASES = [("pms_9_2", 1), ("pms_9_2", 2), ("pms_9_2", 3), ("pms_13_4", 1)]
+# quorum (l,d,q)-motif sets: Q1 and the brute force Q0 must agree; the set
+# is stored as its size and the hash of its codes (little-endian uint64)
+QCASES = [("pms_9_2", 1, 10), ("pms_9_2", 1, 15), ("pms_9_2", 2, 5)]
 
 
 def main():
@@ -46,5 +50,32 @@ def main():
         print(name, seed, len(o1), "O1 %.1fs O0 %.1fs" % (t1 - t0, t2 - t1))
 
 
+def main_quorum():
+    for name, seed, q in QCASES:
+        inst = pmsgen.plain(name, seed)
+        q1 = oracle.q1(inst.seqs, inst.n, inst.m, inst.l, inst.d, q)
+        q0 = oracle.q0(inst.seqs, inst.n, inst.m, inst.l, inst.d, q)
+        assert list(q1) == list(q0), (name, seed, q)
+        path = os.path.join(HERE, "%s_seed%d_q%d.txt" % (name, seed, q))
+        with open(path, "w") as f:
+            f.write("# Exact (l,d,q)-motif set of one synthetic planted instance,\n")
+            f.write("# written by tests/golden/make_golden.py from the CPU oracle\n")
+            f.write("# (Q1, Observation 3.1, and brute-force Q0 agree).\n")
+            f.write("config = %s\nseed = %d\nq = %d\n" % (name, seed, q))
+            f.write("n = %d\nm = %d\nl = %d\nd = %d\n"
+                    % (inst.n, inst.m, inst.l, inst.d))
+            f.write("input_sha256 = %s\n" % hashlib.sha256(inst.seqs).hexdigest())
+            f.write("count = %d\n" % len(q1))
+            f.write("codes_sha256 = %s\n" % hashlib.sha256(
+                q1.astype("<u8").tobytes()).hexdigest())
+            f.write("first = %s\n" % ",".join(str(int(v)) for v in q1[:8]))
+            f.write("last = %s\n" % ",".join(str(int(v)) for v in q1[-8:]))
+        print(name, seed, q, len(q1))
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "quorum":
+        main_quorum()
+    else:
+        main()
+        main_quorum()
