@@ -119,6 +119,28 @@ int pms_solve_device(pms_ctx *ctx, const uint8_t *d_seqs, int n, int m,
                      int l, int d, void *stream, uint64_t *d_out, size_t cap,
                      size_t *count);
 
+/*
+ * Quorum motifs (Definition 5 and the qPMS definition, Sec. 1.2.5): every
+ * l-mer M such that at least q of the n strings have an l-mer within
+ * Hamming distance d of M. q = n is exactly pms_solve. Same arguments,
+ * layout, ownership and output as pms_solve, plus q. Runs the tiled path
+ * with a per-code count of strings without a d-neighbour (tile suffix at
+ * most 8 bases). PMS_EINVAL when q < 1 or q > n, when n - q > 30, when the
+ * context's path is forced to PMS_PATH_FILTER or PMS_PATH_BITSET, or when
+ * l < 3 or l > 21 (more than 4^13 tiles). The output can be large (a
+ * sizeable fraction of 4^l codes when q is small): it is sized on the
+ * device before it is copied.
+ */
+int pms_solve_quorum(pms_ctx *ctx, const char *seqs, int n, int m, int l,
+                     int d, int q, const uint64_t **motifs, size_t *count);
+
+/* pms_solve_quorum with input and output in device memory, as
+ * pms_solve_device (PMS_ENOMEM with *count = the size needed when cap is
+ * too small). */
+int pms_solve_quorum_device(pms_ctx *ctx, const uint8_t *d_seqs, int n,
+                            int m, int l, int d, int q, void *stream,
+                            uint64_t *d_out, size_t cap, size_t *count);
+
 /* One instance of a batch or a serving request. seqs: n*m host bytes. */
 typedef struct {
     const char *seqs;

@@ -100,6 +100,10 @@ def load_library(path: str = LIB_PATH):
         "pms_solve": (i, [vp, ctypes.c_char_p, i, i, i, i,
                           P(P(ctypes.c_uint64)), P(sz)]),
         "pms_solve_device": (i, [vp, vp, i, i, i, i, vp, vp, sz, P(sz)]),
+        "pms_solve_quorum": (i, [vp, ctypes.c_char_p, i, i, i, i, i,
+                                 P(P(ctypes.c_uint64)), P(sz)]),
+        "pms_solve_quorum_device": (i, [vp, vp, i, i, i, i, i, vp, vp, sz,
+                                        P(sz)]),
         "pms_solve_batch": (i, [vp, P(CInstance), i, P(CResult)]),
         "pms_submit": (i, [vp, P(CInstance), P(u64)]),
         "pms_poll": (i, [vp, u64, P(CResult)]),
@@ -219,6 +223,38 @@ class Context:
                                         m, l, d, ctypes.c_void_p(stream),
                                         ctypes.c_void_p(d_out), cap,
                                         ctypes.byref(cnt))
+        if rc == PMS_ENOMEM and cnt.value > cap:
+            err = PmsError(rc, self._lib.pms_last_error(self._h).decode())
+            err.needed = cnt.value
+            raise err
+        self._check(rc)
+        return cnt.value
+
+    def solve_quorum(self, seqs, n: int, m: int, l: int, d: int,
+                     q: int) -> np.ndarray:
+        """(l,d,q)-motifs: l-mers with a d-neighbour in at least q strings."""
+        buf = _as_bytes(seqs)
+        if len(buf) != n * m:
+            raise ValueError("seqs holds %d bytes, expected n*m=%d"
+                             % (len(buf), n * m))
+        ptr = ctypes.POINTER(ctypes.c_uint64)()
+        cnt = ctypes.c_size_t(0)
+        self._check(self._lib.pms_solve_quorum(self._h, buf, n, m, l, d, q,
+                                               ctypes.byref(ptr),
+                                               ctypes.byref(cnt)))
+        if cnt.value == 0:
+            return np.zeros(0, dtype=np.uint64)
+        return np.ctypeslib.as_array(ptr, shape=(cnt.value,)).copy()
+
+    def solve_quorum_device(self, d_seqs: int, n: int, m: int, l: int,
+                            d: int, q: int, d_out: int, cap: int,
+                            stream: int = 0) -> int:
+        """Device-resident quorum solve (as solve_device)."""
+        cnt = ctypes.c_size_t(0)
+        rc = self._lib.pms_solve_quorum_device(
+            self._h, ctypes.c_void_p(d_seqs), n, m, l, d, q,
+            ctypes.c_void_p(stream), ctypes.c_void_p(d_out), cap,
+            ctypes.byref(cnt))
         if rc == PMS_ENOMEM and cnt.value > cap:
             err = PmsError(rc, self._lib.pms_last_error(self._h).decode())
             err.needed = cnt.value

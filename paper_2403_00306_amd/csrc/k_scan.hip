@@ -9,6 +9,8 @@
 // order, so it sorts them (LSD radix sort on device, 8 bits per pass).
 #include "pms_internal.h"
 
+#include <algorithm>
+
 namespace pms {
 
 constexpr int kScanPer = 16;
@@ -141,7 +143,9 @@ hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out,
 }
 
 // Move every tile's block of codes from the heap to its final position.
-// Small blocks are copied by one thread; large ones by the whole group.
+// Small blocks are copied by one thread (in the groups with blockIdx.y 0);
+// large ones by whole groups, each of the gridDim.y groups that share a
+// blockIdx.x taking an interleaved slice.
 __global__ __launch_bounds__(kTPB) void
 k_gather(const uint32_t *tile_cnt, const uint64_t *heap_off,
          const uint64_t *tile_pos, const uint64_t *heap, uint64_t ntiles,
@@ -163,9 +167,11 @@ k_gather(const uint32_t *tile_cnt, const uint64_t *heap_off,
                 // the caller sees the overflow and runs again
                 if (pos + cnt <= cap && heap_off[t] + cnt <= heap_cap) {
                     if (cnt <= 32) {
-                        const uint64_t src = heap_off[t];
-                        for (uint32_t i = 0; i < cnt; i++)
-                            out[pos + i] = heap[src + i];
+                        if (blockIdx.y == 0) {
+                            const uint64_t src = heap_off[t];
+                            for (uint32_t i = 0; i < cnt; i++)
+                                out[pos + i] = heap[src + i];
+                        }
                     } else {
                         big[atomicAdd(&nbig, 1)] = t;
                     }
@@ -178,7 +184,9 @@ k_gather(const uint32_t *tile_cnt, const uint64_t *heap_off,
             const uint64_t tt = big[b];
             const uint32_t cnt = tile_cnt[tt];
             const uint64_t src = heap_off[tt], dst = tile_pos[tt];
-            for (uint32_t i = threadIdx.x; i < cnt; i += kTPB)
+            // the blockIdx.y-th of gridDim.y interleaved slices
+            for (uint32_t i = blockIdx.y * kTPB + threadIdx.x; i < cnt;
+                 i += kTPB * gridDim.y)
                 out[dst + i] = heap[src + i];
         }
         __syncthreads();
@@ -196,7 +204,11 @@ hipError_t launch_gather(const uint32_t *tile_cnt, const uint64_t *heap_off,
     uint64_t blocks = (ntiles + kTPB - 1) / kTPB;
     if (blocks > 4096)
         blocks = 4096;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(kTPB), 0, st,
+    // few tiles (possibly large ones): split each large tile's copy over
+    // up to 64 blocks so that the grid still has ~4096 blocks
+    const unsigned ys = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>(64, 4096 / blocks));
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks, ys), dim3(kTPB), 0, st,
                        tile_cnt, heap_off, tile_pos, heap, ntiles, out,
                        out_cap, heap_cap);
     return hipGetLastError();

@@ -584,9 +584,125 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         sh.U[w] = 0;
 }
 
-__global__ __launch_bounds__(kTPB, 4) void
-k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
-        uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
+// One tile of the quorum path (q < n, Definition 5): every code of the tile
+// keeps a count of the strings so far without a d-neighbour of it, bit-sliced
+// (plane p holds bit p of the counts of 64 codes) in registers. A code stays
+// live while its count is at most n - q; a string ORs its sphere union into
+// U as on the plain path and every live code outside U counts one more miss.
+// The tile stops when no code is live; after the last string the live codes
+// are exactly the (l,d,q)-motifs of the tile.
+constexpr int kQWords = (1 << (2 * (kQuorumMaxSuffix - 3))) / kTPB;
+constexpr int kQPlanes = 5;   // counts 0..kQuorumMaxMiss + 1
+static_assert(kQWords >= 1 && (kQuorumMaxMiss + 1) < (1 << kQPlanes),
+              "quorum counters");
+
+__device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
+                                const Tables &tb, StatAcc &acc)
+{
+    const int tid = threadIdx.x;
+    const int s = I.s, q = s - 3, pl = I.l - s;
+    const int W = 1 << (2 * q);
+    const int T = I.n - I.q;                  // misses a motif may have
+    uint32_t Phi, Plo;
+    prefix_planes(t, pl, Phi, Plo);
+    const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
+    __syncthreads();   // the previous tile may still be reading sh.U
+
+    unsigned long long C[kQPlanes][kQWords];
+    unsigned long long live[kQWords];
+#pragma unroll
+    for (int k = 0; k < kQWords; k++) {
+        live[k] = (tid + k * kTPB < W) ? ~0ull : 0ull;
+#pragma unroll
+        for (int p = 0; p < kQPlanes; p++)
+            C[p][k] = 0;
+    }
+    bool any = true;
+    for (int si = 0; si < I.n; si++) {
+        const int seq = uni(I.order[si]);
+        const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
+                                                  sh, tb);
+        int nz = 0;
+#pragma unroll
+        for (int k = 0; k < kQWords; k++) {
+            const int w = tid + k * kTPB;
+            if (w < W) {
+                const uint32_t pw = wpos((uint32_t)w);
+                const unsigned long long u = sh.U[pw];
+                sh.U[pw] = 0;
+                // add 1 to the count of every live code outside U
+                unsigned long long carry = live[k] & ~u;
+#pragma unroll
+                for (int p = 0; p < kQPlanes; p++) {
+                    const unsigned long long c2 = C[p][k] & carry;
+                    C[p][k] ^= carry;
+                    carry = c2;
+                }
+                // count > T, compared from the top bit down
+                unsigned long long gt = 0, eq = ~0ull;
+#pragma unroll
+                for (int p = kQPlanes - 1; p >= 0; p--) {
+                    if ((T >> p) & 1) {
+                        eq &= C[p][k];
+                    } else {
+                        gt |= eq & C[p][k];
+                        eq &= ~C[p][k];
+                    }
+                }
+                live[k] &= ~gt;
+                nz |= live[k] != 0;
+            }
+        }
+        if (tid == 0) {
+            acc.passes++;
+            acc.marks += mk;
+        }
+        if (!__syncthreads_or(nz)) {
+            any = false;
+            break;
+        }
+    }
+    if (tid == 0)
+        acc.tiles++;
+    if (!any) {
+        if (tid == 0) {
+            I.tile_cnt[t] = 0;
+            I.tile_heap_off[t] = 0;
+        }
+        return;
+    }
+    unsigned long long cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kQWords; k++) {
+        const int w = tid + k * kTPB;
+        if (w < W) {
+            sh.U[w] = live[k];
+            cnt += __popcll(live[k]);
+        }
+    }
+    const unsigned long long total = block_sum64(cnt, sh.red64);
+    if (tid == 0) {
+        const unsigned long long off = atomicAdd(I.heap_top, total);
+        sh.bcast = off;
+        I.tile_cnt[t] = (uint32_t)total;
+        I.tile_heap_off[t] = off;
+    }
+    __syncthreads();
+    const unsigned long long off = uni(sh.bcast);
+    const bool fits = off + total <= I.heap_cap;
+    emit_words(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
+    __syncthreads();
+    for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
+        sh.U[w] = 0;
+}
+
+// Persistent loop shared by the tiled kernels: workgroups take work items
+// (tile ranges) from a counter until none is left.
+template <bool Quorum>
+__device__ __forceinline__ void drain_items(const InstDev *insts,
+                                            const WorkItem *items, int nitems,
+                                            uint64_t chunk, unsigned int *next,
+                                            const Tables &tb, TileStats *stats)
 {
     __shared__ TileShared sh;
     __shared__ int s_item;
@@ -613,8 +729,12 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
             w.t1 = min(w.t0 + chunk, insts[0].ntiles);
         }
         const InstDev I = insts[w.inst];
-        for (uint64_t t = w.t0; t < w.t1; t++)
-            run_tile(I, t, sh, tb, acc);
+        for (uint64_t t = w.t0; t < w.t1; t++) {
+            if (Quorum)
+                run_tile_quorum(I, t, sh, tb, acc);
+            else
+                run_tile(I, t, sh, tb, acc);
+        }
     }
     if (threadIdx.x == 0 && stats) {
         atomicAdd(&stats->passes, acc.passes);
@@ -622,6 +742,21 @@ k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
         atomicAdd(&stats->ftests, acc.ftests);
         atomicAdd(&stats->tiles, acc.tiles);
     }
+}
+
+__global__ __launch_bounds__(kTPB, 4) void
+k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
+        uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
+{
+    drain_items<false>(insts, items, nitems, chunk, next, tb, stats);
+}
+
+__global__ __launch_bounds__(kTPB, 4) void
+k_tiled_quorum(const InstDev *insts, const WorkItem *items, int nitems,
+               uint64_t chunk, unsigned int *next, Tables tb,
+               TileStats *stats)
+{
+    drain_items<true>(insts, items, nitems, chunk, next, tb, stats);
 }
 
 hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
@@ -633,6 +768,28 @@ hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
     hipLaunchKernelGGL(k_tiled, dim3(grid), dim3(kTPB), 0, st, d_insts,
                        d_items, nitems, chunk, d_next, tb, stats);
     return hipGetLastError();
+}
+
+hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,
+                               int nitems, uint64_t chunk,
+                               unsigned int *d_next, Tables tb,
+                               TileStats *stats, int grid, hipStream_t st)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_tiled_quorum, dim3(grid), dim3(kTPB), 0, st,
+                       d_insts, d_items, nitems, chunk, d_next, tb, stats);
+    return hipGetLastError();
+}
+
+int tiled_quorum_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled_quorum,
+                                                     kTPB, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
 }
 
 int tiled_blocks_per_cu()

@@ -115,6 +115,7 @@ InstDev make_desc(char *base, const InstLayout &o, const uint8_t *seqs,
     I.s = s;
     I.surv_t = surv_t;
     I.wpr = (m + 31) / 32;
+    I.q = n;
     return I;
 }
 
@@ -364,7 +365,7 @@ namespace pms {
 // d_out_ext (cap_ext codes) if given, else in ctx-owned memory.
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,
-               size_t cap_ext, int forced_path, SolveOut *res)
+               size_t cap_ext, int forced_path, SolveOut *res, int q)
 {
     const double t0 = now_ms();
     res->d_out = nullptr;
@@ -373,7 +374,27 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
     if (rc)
         return c->fail(rc, "bad shape n=%d m=%d l=%d d=%d (need n>=1, "
                            "1<=l<=32, l<=m, 0<=d<l)", n, m, l, d);
+    if (q < 0 || q > n)
+        return c->fail(PMS_EINVAL, "quorum q=%d outside 1..n=%d", q, n);
+    const bool quorum = q > 0 && q < n;
+    if (quorum) {
+        if (n - q > kQuorumMaxMiss)
+            return c->fail(PMS_EINVAL, "quorum: n-q=%d above %d", n - q,
+                           kQuorumMaxMiss);
+        if (forced_path == PMS_PATH_FILTER || forced_path == PMS_PATH_BITSET)
+            return c->fail(PMS_EINVAL, "quorum (q<n) runs the tiled path "
+                           "only");
+        forced_path = PMS_PATH_TILED;
+    }
     Plan P = c->plan(n, m, l, d, forced_path);
+    if (quorum) {
+        P.s = std::min(P.s, kQuorumMaxSuffix);
+        if (l < 3 || P.s < 3 || l - P.s > kMaxTilePrefix)
+            return c->fail(PMS_EINVAL, "quorum: l=%d outside 3..%d", l,
+                           kQuorumMaxSuffix + kMaxTilePrefix);
+        P.path = PMS_PATH_TILED;
+        P.ntiles = pow4(l - P.s);
+    }
     pms_stats S{};
     S.path = P.path;
     S.tile_suffix = (P.path == PMS_PATH_FILTER) ? 0 : P.s;
@@ -385,6 +406,12 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
     if (P.path == PMS_PATH_BITSET && (l - 3 > 28 || pow4(l - 3) * 8 >
                                                         c->budget))
         return c->fail(PMS_ENOMEM, "bitset path needs 4^%d/8 bytes", l);
+    const auto shape_key = std::make_tuple(n, m, l, d, quorum ? q : n);
+    if (P.path != PMS_PATH_BITSET) {
+        auto hn = c->heap_need.find(shape_key);
+        if (hn != c->heap_need.end())
+            heap_cap = std::max(heap_cap, hn->second);
+    }
 
     for (int attempt = 0; attempt < 5; attempt++) {
         const bool own_out = (d_out_ext == nullptr) &&
@@ -400,6 +427,8 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         char *base = (char *)c->arena.p;
         InstDev I = make_desc(base, lay, d_seqs, n, m, l, d, P.s, P.surv_t,
                               ntiles, heap_cap);
+        if (quorum)
+            I.q = q;
         InstDev *d_inst = (InstDev *)(base + desc_off);
         TileStats *d_stats = (TileStats *)(base + stats_off);
         unsigned long long *d_next = (unsigned long long *)(base + next_off);
@@ -469,6 +498,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                 S.retries++;
                 continue;
             }
+            c->heap_need[shape_key] = hp[1] + 1024;
             const uint64_t total = hp[1];
             if (total > dst_cap) {
                 res->count = total;
@@ -490,9 +520,15 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             const uint64_t max_items = 1u << 20;
             const uint64_t chunk = (ntiles + max_items - 1) / max_items;
             const uint64_t nitems = (ntiles + chunk - 1) / chunk;
-            HIPCHK(c, launch_tiled(d_inst, nullptr, (int)nitems, chunk,
-                                   (unsigned int *)d_next, c->tb, d_stats,
-                                   grid_for(c, c->tiled_bpc), st));
+            if (quorum)
+                HIPCHK(c, launch_tiled_quorum(d_inst, nullptr, (int)nitems,
+                                              chunk, (unsigned int *)d_next,
+                                              c->tb, d_stats,
+                                              grid_for(c, c->tiled_q_bpc), st));
+            else
+                HIPCHK(c, launch_tiled(d_inst, nullptr, (int)nitems, chunk,
+                                       (unsigned int *)d_next, c->tb, d_stats,
+                                       grid_for(c, c->tiled_bpc), st));
             S.main_launches = 1;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
             HIPCHK(c, launch_scan_u32(I.tile_cnt, ntiles, tile_pos,
@@ -516,6 +552,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                 S.retries++;
                 continue;
             }
+            c->heap_need[shape_key] = hp[1] + 1024;
             if (hp[0] > dst_cap) {
                 res->count = hp[0];
                 return c->fail(PMS_ENOMEM, "output capacity %llu < %llu",
@@ -694,6 +731,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     }
     c->n_cu = prop.multiProcessorCount;
     c->tiled_bpc = tiled_blocks_per_cu();
+    c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
     c->filter_bpc = filter_blocks_per_cu();
     size_t freeb = 0, totb = 0;
     if (hipMemGetInfo(&freeb, &totb) != hipSuccess) {
@@ -835,6 +873,54 @@ int pms_solve_device(pms_ctx *c, const uint8_t *d_seqs, int n, int m, int l,
     SolveOut r{};
     int rc = solve_core(c, nullptr, d_seqs, n, m, l, d, st, d_out, cap,
                         c->opt.path, &r);
+    *count = r.count;
+    return rc;
+}
+
+int pms_solve_quorum(pms_ctx *c, const char *seqs, int n, int m, int l,
+                     int d, int q, const uint64_t **motifs, size_t *count)
+{
+    if (!c)
+        return PMS_EINVAL;
+    if (!seqs || !motifs || !count)
+        return c->fail(PMS_EINVAL, "NULL argument");
+    *motifs = nullptr;
+    *count = 0;
+    if (q < 1 || q > n)
+        return c->fail(PMS_EINVAL, "quorum q=%d outside 1..n=%d", q, n);
+    hipSetDevice(c->device);
+    SolveOut r{};
+    int rc = solve_core(c, seqs, nullptr, n, m, l, d, c->stream, nullptr, 0,
+                        c->opt.path, &r, q);
+    if (rc)
+        return rc;
+    c->host_out.resize(r.count);
+    if (r.count) {
+        HIPCHK(c, hipMemcpyAsync(c->host_out.data(), r.d_out, r.count * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *motifs = c->host_out.data();
+    }
+    *count = r.count;
+    return PMS_OK;
+}
+
+int pms_solve_quorum_device(pms_ctx *c, const uint8_t *d_seqs, int n, int m,
+                            int l, int d, int q, void *stream, uint64_t *d_out,
+                            size_t cap, size_t *count)
+{
+    if (!c)
+        return PMS_EINVAL;
+    if (!d_seqs || !count || !d_out)
+        return c->fail(PMS_EINVAL, "NULL argument");
+    *count = 0;
+    if (q < 1 || q > n)
+        return c->fail(PMS_EINVAL, "quorum q=%d outside 1..n=%d", q, n);
+    hipSetDevice(c->device);
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    SolveOut r{};
+    int rc = solve_core(c, nullptr, d_seqs, n, m, l, d, st, d_out, cap,
+                        c->opt.path, &r, q);
     *count = r.count;
     return rc;
 }

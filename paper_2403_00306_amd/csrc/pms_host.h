@@ -10,6 +10,7 @@
 #include <atomic>
 #include <chrono>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -77,7 +78,7 @@ struct pms_ctx {
     std::string err;
     std::string tune_path;
     hipStream_t stream = nullptr;
-    int n_cu = 0, tiled_bpc = 1, filter_bpc = 1;
+    int n_cu = 0, tiled_bpc = 1, filter_bpc = 1, tiled_q_bpc = 1;
     size_t budget = 0;
     std::atomic<size_t> held{0};
 
@@ -111,6 +112,9 @@ struct pms_ctx {
     uint64_t b_graph_replays = 0;
     uint64_t b_heap_key = 0;      // shape of the last batch
     uint64_t b_heap_need = 0;     // heap it needed (with slack)
+    // single solves: heap entries a shape (n, m, l, d, q) last needed, so
+    // that repeated calls start large enough instead of rerunning
+    std::map<std::tuple<int, int, int, int, int>, uint64_t> heap_need;
 
     pms::Server *srv = nullptr;
 
@@ -131,9 +135,10 @@ struct pms_ctx {
     } while (0)
 
 namespace pms {
+// q = 0 (or q = n): plain PMS; 1 <= q < n: (l,d,q)-motifs (tiled path).
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,
-               size_t cap_ext, int forced_path, SolveOut *res);
+               size_t cap_ext, int forced_path, SolveOut *res, int q = 0);
 void serve_shutdown(pms_ctx *c);
 void load_tune_cache(pms_ctx *c);
 }  // namespace pms

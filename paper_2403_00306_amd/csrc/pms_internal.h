@@ -17,6 +17,9 @@ constexpr int kWordsPerThread = kMaxWords / kTPB;   // 16
 constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
 constexpr int kDefaultSurv = 64;   // default threshold to enter it
+constexpr int kQuorumMaxSuffix = 8;   // quorum tiles: 4^8 codes, so that
+constexpr int kQuorumMaxMiss = 30;    //   5-bit miss counters of every code
+                                      //   stay in registers (4 words/thread)
 constexpr int kBallDigits = kMaxSuffix - 3;         // 6 word-index digits
 
 // Read-only views of device arrays held in descriptors. The l-mer tables
@@ -81,6 +84,9 @@ struct InstDev {
                              //   concatenated tile space
     uint64_t ntiles;         // 4^(l-s)
     int n, m, l, d, L, s, surv_t, wpr;
+    int q;                   // quorum: a motif needs d-neighbours in at
+                             //   least q strings (q = n: every string)
+    int pad_q;
 };
 
 // A contiguous range of one instance's tiles.
@@ -124,6 +130,13 @@ hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
                         int nitems, uint64_t chunk, unsigned int *d_next,
                         Tables tb, TileStats *stats, int grid, hipStream_t st);
 int tiled_blocks_per_cu();
+// Quorum variant of launch_tiled (instances with q < n, tile suffix at
+// most kQuorumMaxSuffix, n - q at most kQuorumMaxMiss).
+hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,
+                               int nitems, uint64_t chunk,
+                               unsigned int *d_next, Tables tb,
+                               TileStats *stats, int grid, hipStream_t st);
+int tiled_quorum_blocks_per_cu();
 
 // Memory-heavy bitset path: one pass per string over the whole 4^l space.
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
