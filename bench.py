@@ -29,17 +29,23 @@ PEAK_HBM = 8.0e12                   # bytes/s
 OPS_TEST = 3.5
 OPS_PREFIX = 4.0
 OPS_MARK = 2.0
+# quorum path, per 64-code word per pass: the bit-sliced increment (XOR and
+# AND per counter plane) and the compare with n - q (about 2 per plane),
+# 5 planes
+OPS_COUNT = 20.0
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pms_17_6_traffic.json")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, pick: str = "bytes"):
     """HBM bytes per dispatch from the committed counter profile, if it was
-    taken on the current source of that kernel (else None)."""
+    taken on the current source of that kernel (else None). pick: "bytes"
+    (mean over dispatches), "min_bytes" or "max_bytes" (for a kernel that
+    the profiled run launches on two workload sizes)."""
     try:
         from paper_2403_00306_amd import profile_tools
         rec = json.load(open(TRAFFIC_JSON))["kernels"][kernel]
         if rec["source_sha"] == profile_tools.source_hash(kernel):
-            return rec["bytes"]
+            return rec[pick]
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -115,6 +121,66 @@ def batch_bench(pms, pmsgen, np, tune: bool) -> dict:
             "plain_ms": 1000 * t_plain, "batch_kernel_ms": bst["ms_main"],
             "motifs_total": int(sum(len(a) for a in alone)),
             "batched_equals_plain": bool(same), "autotune_s": t_tune}
+
+
+def quorum_bench(pms, pmsgen, np, torch, dev, reps: int = 3) -> dict:
+    """(l,d,q)-motifs at the thesis's q = 10 shape (n = 20, m = 600):
+    device-resident solve time and the quorum kernel's roofline."""
+    res = {}
+    for name, q in (("pms_13_4", 10), ("pms_17_6", 10)):
+        inst = pmsgen.plain(name, 1)
+        n, m, l, d = inst.n, inst.m, inst.l, inst.d
+        d_seqs = torch.frombuffer(bytearray(inst.seqs),
+                                  dtype=torch.uint8).to(dev)
+        ctx = pms.Context(device=0)
+        cap = 1 << 16
+        d_out = torch.empty(cap, dtype=torch.int64, device=dev)
+        try:
+            ctx.solve_quorum_device(d_seqs.data_ptr(), n, m, l, d, q,
+                                    d_out.data_ptr(), cap)
+        except pms.PmsError as e:
+            cap = e.needed
+            del d_out
+            d_out = torch.empty(cap, dtype=torch.int64, device=dev)
+        ctx.solve_quorum_device(d_seqs.data_ptr(), n, m, l, d, q,
+                                d_out.data_ptr(), cap)
+        torch.cuda.synchronize()
+        walls, kms = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            cnt = ctx.solve_quorum_device(d_seqs.data_ptr(), n, m, l, d, q,
+                                          d_out.data_ptr(), cap)
+            walls.append((time.perf_counter() - t0) * 1000.0)
+            st = ctx.stats()
+            kms.append(st["ms_main"])
+        k_ms = float(np.mean(kms))
+        L = m - l + 1
+        words = 4 ** (st["tile_suffix"] - 3)
+        ops = (st["marks"] * OPS_MARK + st["tile_passes"] * L * OPS_PREFIX +
+               st["tile_passes"] * words * OPS_COUNT)
+        achieved = ops / (k_ms / 1000.0)
+        res["%s_q%d" % (name, q)] = {
+            "workload": "(%d,%d,%d)-motifs, n=%d, m=%d, seed 1"
+                        % (l, d, q, n, m),
+            "motifs": int(cnt), "solve_ms": min(walls), "kernel_ms": k_ms,
+            "output_ms": st["ms_output"], "tiles": st["tiles"],
+            "passes": st["tile_passes"], "tile_suffix": st["tile_suffix"],
+            "roofline": {"bound": "alu", "kernel": "k_tiled_quorum",
+                         "achieved": achieved / 1e12,
+                         "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
+                         "frac": achieved / PEAK_ALU_OPS,
+                         # the profiled run launches it at (13,4), then
+                         # at (17,6): smallest and largest dispatches
+                         "traffic": measured_traffic(
+                             "k_tiled_quorum",
+                             "max_bytes" if l >= 17 else "min_bytes"),
+                         "ops_per_launch": ops}}
+        log("quorum %s q=%d: %d motifs, %.2f ms solve, %.2f ms kernel"
+            % (name, q, cnt, min(walls), k_ms))
+        ctx.close()
+        del d_out, d_seqs
+        torch.cuda.empty_cache()
+    return res
 
 
 def serve_bench(pms, pmsgen, np, count: int) -> dict:
@@ -280,6 +346,7 @@ def main():
                          "traffic": measured_traffic("k_bitset_pass"),
                          "algorithmic_bytes": bst["bytes_main"]}}
         bctx.close()
+        extra["quorum"] = quorum_bench(pms, pmsgen, np, torch, dev)
     if not args.no_batch:
         log("batched")
         extra["batched"] = batch_bench(pms, pmsgen, np, not args.no_tune)

@@ -29,6 +29,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.hip",
+                  "k_tiled_quorum": "csrc/k_tiles.hip",
                   "k_filter": "csrc/k_filter.hip"}
 
 
@@ -101,8 +102,14 @@ def main():
         lines.append("| %s | %d | %.3f | %.3f |" % (k, len(f), fm / 1e6,
                                                    wm / 1e6))
         if k in KERNEL_SOURCES:
+            # the i-th dispatch of a kernel is the same bench step in both
+            # runs; a kernel launched on workloads of different sizes also
+            # keeps its smallest and largest dispatch
+            per = [a * 1024.0 * (kf or 1.0) + b * 1024.0 * (kw or 1.0)
+                   for a, b in zip(f, w)]
             traffic[k] = {"fetch_bytes": fm, "write_bytes": wm,
-                          "bytes": fm + wm, "source_sha": source_hash(k)}
+                          "bytes": fm + wm, "min_bytes": min(per),
+                          "max_bytes": max(per), "source_sha": source_hash(k)}
     open(os.path.join(a.out, "%s_traffic.md" % a.name), "w").write(
         "\n".join(lines) + "\n")
     json.dump({"command": a.command, "copy_bytes": a.copy_bytes,
