@@ -183,6 +183,38 @@ def quorum_bench(pms, pmsgen, np, torch, dev, reps: int = 3) -> dict:
     return res
 
 
+def hard_bench(pms, pmsgen, np) -> dict:
+    """The thesis's harder planted instances (Table 3.3 shapes, n = 20,
+    m = 600, seed 1) on the tiled path: solve time and k_tiled's roofline."""
+    res = {}
+    for l, d in ((19, 7), (21, 8), (23, 9)):
+        inst = pmsgen.planted(1, 20, 600, l, d)
+        with pms.Context(device=0, path=pms.PATH_TILED) as c:
+            t0 = time.perf_counter()
+            got = c.solve(inst.seqs, 20, 600, l, d)
+            wall = (time.perf_counter() - t0) * 1000.0
+            st = c.stats()
+        L = 600 - l + 1
+        ops = (st["marks"] * OPS_MARK + st["tile_passes"] * L * OPS_PREFIX +
+               st["filter_tests"] * OPS_TEST)
+        plant = 0
+        for ch in inst.motif:
+            plant = 4 * plant + b"ACGT".index(ch)
+        res["pms_%d_%d" % (l, d)] = {
+            "workload": "planted (%d,%d), n=20, m=600, seed 1" % (l, d),
+            "solve_ms": wall, "kernel_ms": st["ms_main"],
+            "motifs": int(len(got)),
+            "planted_found": bool(plant in set(int(v) for v in got)),
+            "tiles": st["tiles"], "passes": st["tile_passes"],
+            "roofline": {"bound": "alu", "kernel": "k_tiled",
+                         "achieved": ops / (st["ms_main"] / 1000.0) / 1e12,
+                         "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
+                         "frac": ops / (st["ms_main"] / 1000.0)
+                         / PEAK_ALU_OPS}}
+        log("hard (%d,%d): %.1f ms, %d motifs" % (l, d, wall, len(got)))
+    return res
+
+
 def serve_bench(pms, pmsgen, np, count: int) -> dict:
     """Poisson request stream through the continuous-batching engine:
     first a saturation pass (all requests at t=0) gives the capacity C;
@@ -248,6 +280,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-hard", action="store_true",
+                    help="skip the (19,7)/(21,8)/(23,9) leg (~17 s)")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -347,6 +381,8 @@ def main():
                          "algorithmic_bytes": bst["bytes_main"]}}
         bctx.close()
         extra["quorum"] = quorum_bench(pms, pmsgen, np, torch, dev)
+        if not args.no_hard:
+            extra["hard"] = hard_bench(pms, pmsgen, np)
     if not args.no_batch:
         log("batched")
         extra["batched"] = batch_bench(pms, pmsgen, np, not args.no_tune)

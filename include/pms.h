@@ -127,7 +127,7 @@ int pms_solve_device(pms_ctx *ctx, const uint8_t *d_seqs, int n, int m,
  * with a per-code count of strings without a d-neighbour (tile suffix at
  * most 8 bases). PMS_EINVAL when q < 1 or q > n, when n - q > 30, when the
  * context's path is forced to PMS_PATH_FILTER or PMS_PATH_BITSET, or when
- * l < 3 or l > 21 (more than 4^13 tiles). The output can be large (a
+ * l < 3 or l > 22 (more than 4^14 tiles). The output can be large (a
  * sizeable fraction of 4^l codes when q is small): it is sized on the
  * device before it is copied.
  */
@@ -172,7 +172,7 @@ int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
  * bounded slice per launch, so requests join and leave between launches.
  * *ticket identifies the request. PMS_EBUSY if the waiting queue is full;
  * PMS_EINVAL for a bad shape, for a shape the tiled path does not suit
- * (l < 3, or more than 4^13 tiles; use pms_solve) and PMS_ENOMEM for a
+ * (l < 3, or more than 4^14 tiles; use pms_solve) and PMS_ENOMEM for a
  * request larger than the serving pool (all checked before queueing).
  * Bad bytes are found on the device: the result's status is PMS_EBASE.
  * While requests are in flight, do not call pms_solve* or pms_autotune on

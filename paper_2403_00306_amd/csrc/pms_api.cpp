@@ -280,7 +280,7 @@ Plan pms_ctx::plan(int n, int m, int l, int d, int forced)
     else
         p.path = (p.cost_tiled < p.cost_filter) ? PMS_PATH_TILED
                                                 : PMS_PATH_FILTER;
-    // beyond 4^13 tiles the pattern-driven paths are out of reach (every
+    // beyond 4^14 tiles the pattern-driven paths are out of reach (every
     // tile pays at least one pass of prefix tests)
     if ((p.path == PMS_PATH_TILED || p.path == PMS_PATH_BITSET) &&
         (l < 3 || p.s < 3 || l - p.s > kMaxTilePrefix))

@@ -21,7 +21,7 @@ namespace pms {
 
 constexpr size_t kPinnedDescBytes = 1 << 20;   // descriptor + string order
 constexpr size_t kPinnedHcEntries = 1 << 16;   // per-reference test counts
-constexpr int kMaxTilePrefix = 13;             // at most 4^13 tiles
+constexpr int kMaxTilePrefix = 14;             // at most 4^14 tiles
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 inline uint64_t pow4(int k) { return k <= 0 ? 1ull : (1ull << (2 * k)); }

@@ -119,7 +119,7 @@ def test_quorum_edges(ctx):
         ctx.solve_quorum(seqs, 32, 30, 6, 1, 1)          # n - q = 31
     seqs = bytes(rng.choice(ACGT) for _ in range(4 * 40))
     with pytest.raises(pms.PmsError):
-        ctx.solve_quorum(seqs, 4, 40, 22, 3, 2)          # 4^14 tiles
+        ctx.solve_quorum(seqs, 4, 40, 23, 3, 2)          # 4^15 tiles
     with pms.Context(path=pms.PATH_FILTER) as c2:
         with pytest.raises(pms.PmsError):
             c2.solve_quorum(inst.seqs, inst.n, inst.m, 9, 2, 10)
