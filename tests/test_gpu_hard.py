@@ -61,7 +61,6 @@ def test_hard_21_8():
     check(inst, got)
 
 
-@pytest.mark.slow
 def test_hard_23_9():
     inst = pmsgen.planted(1, 20, 600, 23, 9)
     say("hard (23,9) tiled, 4^14 tiles")
