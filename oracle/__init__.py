@@ -57,6 +57,16 @@ def _load():
                 ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                 ctypes.c_int, ctypes.c_int, ctypes.c_int,
                 ctypes.POINTER(u64p), ctypes.POINTER(ctypes.c_size_t)]
+        lib.oracle_s1.restype = ctypes.c_int
+        lib.oracle_s1.argtypes = [
+            ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.POINTER(u64p), ctypes.POINTER(ctypes.c_size_t)]
+        lib.oracle_s0.restype = ctypes.c_int
+        lib.oracle_s0.argtypes = [
+            ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.POINTER(u64p), ctypes.POINTER(ctypes.c_size_t)]
         lib.oracle_hit_count.restype = ctypes.c_int
         lib.oracle_hit_count.argtypes = [
             ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -173,6 +183,33 @@ def q0(seqs, n, m, l, d, q, threads=0) -> np.ndarray:
     """(l,d,q)-motifs by brute force over all 4^l codes."""
     return _quorum(_load().oracle_q0, "oracle_q0", seqs, n, m, l, d, q,
                    threads)
+
+
+def s1(seqs, alphabet: bytes, n, m, l, d, threads=0) -> np.ndarray:
+    """(l,d)-motifs over the given alphabet, sample-driven; codes in base
+    len(alphabet), first letter in the top digit."""
+    buf = _seq_bytes(seqs)
+    assert len(buf) == n * m
+    out = ctypes.POINTER(ctypes.c_uint64)()
+    count = ctypes.c_size_t(0)
+    rc = _load().oracle_s1(buf, bytes(alphabet), len(alphabet), n, m, l, d,
+                           threads, ctypes.byref(out), ctypes.byref(count))
+    if rc != OR_OK:
+        raise OracleError(rc, "oracle_s1")
+    return _take(out, count.value)
+
+
+def s0(seqs, alphabet: bytes, n, m, l, d) -> np.ndarray:
+    """(l,d)-motifs over the given alphabet by brute force (small spaces)."""
+    buf = _seq_bytes(seqs)
+    assert len(buf) == n * m
+    out = ctypes.POINTER(ctypes.c_uint64)()
+    count = ctypes.c_size_t(0)
+    rc = _load().oracle_s0(buf, bytes(alphabet), len(alphabet), n, m, l, d,
+                           ctypes.byref(out), ctypes.byref(count))
+    if rc != OR_OK:
+        raise OracleError(rc, "oracle_s0")
+    return _take(out, count.value)
 
 
 def hit_count(seqs, n, m, l, d, code) -> int:

@@ -44,6 +44,12 @@
  *      character with every l-mer of every string, kept when at least q
  *      strings have a d-neighbour.
  *
+ * Other alphabets (Sec. 1.2.5 defines the problem over any alphabet Sigma;
+ * Table 3.1 gives n_B for any |Sigma|): S1 and S0 are O1 and O0 over an
+ * alphabet of sigma letters given by the caller (letter code = its index
+ * in the alphabet string), with codes in base sigma, first letter in the
+ * top digit, and character-by-character distances.
+ *
  * O1 also counts the canonical number of Hamming tests, H_canon: for each
  * enumerated candidate (with multiplicity over references x), (m-l+1) times
  * the number of strings s_2..s_n examined, up to and including the first one
@@ -837,6 +843,237 @@ int oracle_hit_count(const char *seqs, int n, int m, int l, int d,
         hits += ok;
     }
     return hits;
+}
+
+/* ---- any alphabet: S1 (sample-driven) and S0 (brute force) ------------- */
+
+typedef struct {
+    signed char map[256];   /* byte -> letter code, -1 if not in alphabet */
+    int sigma;
+} alpha_t;
+
+static int alpha_setup(alpha_t *A, const char *alphabet, int sigma)
+{
+    if (!alphabet || sigma < 2 || sigma > 32)
+        return OR_EINVAL;
+    memset(A->map, -1, sizeof(A->map));
+    for (int i = 0; i < sigma; i++) {
+        unsigned char ch = (unsigned char)alphabet[i];
+        if (A->map[ch] >= 0)
+            return OR_EINVAL; /* repeated letter */
+        A->map[ch] = (signed char)i;
+    }
+    A->sigma = sigma;
+    return OR_OK;
+}
+
+/* sigma^l must fit in 64 bits: codes are base-sigma integers */
+static int alpha_space(int sigma, int l, uint64_t *space)
+{
+    __uint128_t v = 1;
+    for (int j = 0; j < l; j++) {
+        v *= (unsigned)sigma;
+        if (v > ((__uint128_t)1 << 64))
+            return OR_EINVAL;
+    }
+    *space = (v == ((__uint128_t)1 << 64)) ? 0 : (uint64_t)v;
+    return OR_OK;
+}
+
+/* Definition 3 with an early stop: 1 if the two l-mers differ in at most
+ * d positions. */
+static int within_d(const unsigned char *a, const unsigned char *b, int l,
+                    int d)
+{
+    int h = 0;
+    for (int k = 0; k < l; k++)
+        if (a[k] != b[k] && ++h > d)
+            return 0;
+    return 1;
+}
+
+typedef struct {
+    const unsigned char *letters; /* n*m letter codes */
+    int n, m, l, d, sigma, nthreads, tid;
+    vec64 out;
+} s1_job;
+
+static uint64_t code_sigma(const unsigned char *M, int l, int sigma)
+{
+    uint64_t c = 0;
+    for (int j = 0; j < l; j++)
+        c = c * (uint64_t)sigma + M[j];
+    return c;
+}
+
+/* A candidate is kept when every string s_2..s_n has an l-mer within d. */
+static int s1_test(const s1_job *J, const unsigned char *M)
+{
+    for (int i = 1; i < J->n; i++) {
+        const unsigned char *s = J->letters + (size_t)i * J->m;
+        int hit = 0;
+        for (int j = 0; j + J->l <= J->m && !hit; j++)
+            hit = within_d(M, s + j, J->l, J->d);
+        if (!hit)
+            return 0;
+    }
+    return 1;
+}
+
+/* T_d(x) over sigma letters: a node that last changed position p has
+ * children changing one position p' > p to one of the sigma-1 others. */
+static void s1_ball(s1_job *J, unsigned char *M, const unsigned char *x,
+                    int from, int budget)
+{
+    if (s1_test(J, M))
+        vpush(&J->out, code_sigma(M, J->l, J->sigma));
+    if (budget == 0)
+        return;
+    for (int p = from; p < J->l; p++) {
+        for (int b = 0; b < J->sigma; b++) {
+            if (b == x[p])
+                continue;
+            M[p] = (unsigned char)b;
+            s1_ball(J, M, x, p + 1, budget - 1);
+        }
+        M[p] = x[p];
+    }
+}
+
+static void *s1_worker(void *arg)
+{
+    s1_job *J = (s1_job *)arg;
+    int L = J->m - J->l + 1;
+    int lo = (int)((long long)L * J->tid / J->nthreads);
+    int hi = (int)((long long)L * (J->tid + 1) / J->nthreads);
+    unsigned char M[32];
+    for (int j = lo; j < hi; j++) {
+        const unsigned char *x = J->letters + j;
+        memcpy(M, x, (size_t)J->l);
+        s1_ball(J, M, x, 0, J->d);
+    }
+    return NULL;
+}
+
+static int alpha_decode(const alpha_t *A, const char *seqs, size_t total,
+                        unsigned char *out)
+{
+    for (size_t k = 0; k < total; k++) {
+        int c = A->map[(unsigned char)seqs[k]];
+        if (c < 0)
+            return OR_EBASE;
+        out[k] = (unsigned char)c;
+    }
+    return OR_OK;
+}
+
+/* S1: the (l,d)-motifs over the given alphabet, sample-driven (every motif
+ * lies in B(x,d) for an l-mer x of s_1). */
+int oracle_s1(const char *seqs, const char *alphabet, int sigma, int n,
+              int m, int l, int d, int nthreads, uint64_t **out,
+              size_t *count)
+{
+    alpha_t A;
+    uint64_t space;
+    int rc = check_args(n, m, l, d);
+    if (!rc)
+        rc = alpha_setup(&A, alphabet, sigma);
+    if (!rc)
+        rc = alpha_space(sigma, l, &space);
+    if (rc)
+        return rc;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *letters = (unsigned char *)malloc(total);
+    int T = pick_threads(nthreads);
+    int L = m - l + 1;
+    if (T > L)
+        T = L;
+    s1_job *jobs = (s1_job *)calloc((size_t)T, sizeof(s1_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    vec64 *vs = (vec64 *)calloc((size_t)T, sizeof(vec64));
+    if (!letters || !jobs || !th || !vs) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    if ((rc = alpha_decode(&A, seqs, total, letters)))
+        goto done;
+    for (int t = 0; t < T; t++) {
+        s1_job *J = &jobs[t];
+        J->letters = letters;
+        J->n = n;
+        J->m = m;
+        J->l = l;
+        J->d = d;
+        J->sigma = sigma;
+        J->nthreads = T;
+        J->tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, s1_worker, &jobs[t]);
+    s1_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    for (int t = 0; t < T; t++)
+        vs[t] = jobs[t].out;
+    rc = gather_out(vs, T, 1, out, count);
+done:
+    if (jobs)
+        for (int t = 0; t < T; t++)
+            free(jobs[t].out.v);
+    free(vs);
+    free(jobs);
+    free(th);
+    free(letters);
+    return rc;
+}
+
+/* S0: every code of the sigma^l space (small spaces only), kept when every
+ * string has an l-mer within distance d. */
+int oracle_s0(const char *seqs, const char *alphabet, int sigma, int n,
+              int m, int l, int d, uint64_t **out, size_t *count)
+{
+    alpha_t A;
+    uint64_t space;
+    int rc = check_args(n, m, l, d);
+    if (!rc)
+        rc = alpha_setup(&A, alphabet, sigma);
+    if (!rc)
+        rc = alpha_space(sigma, l, &space);
+    if (rc)
+        return rc;
+    if (space == 0 || space > (1ULL << 26))
+        return OR_EINVAL;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *letters = (unsigned char *)malloc(total);
+    vec64 v = {0};
+    if (!letters)
+        return OR_ENOMEM;
+    if ((rc = alpha_decode(&A, seqs, total, letters))) {
+        free(letters);
+        return rc;
+    }
+    unsigned char M[32];
+    for (uint64_t c = 0; c < space; c++) {
+        uint64_t r = c;
+        for (int j = l - 1; j >= 0; j--) {
+            M[j] = (unsigned char)(r % (uint64_t)sigma);
+            r /= (uint64_t)sigma;
+        }
+        int ok = 1;
+        for (int i = 0; i < n && ok; i++) {
+            const unsigned char *s = letters + (size_t)i * m;
+            int hit = 0;
+            for (int j = 0; j + l <= m && !hit; j++)
+                hit = within_d(M, s + j, l, d);
+            ok = hit;
+        }
+        if (ok)
+            vpush(&v, c);
+    }
+    free(letters);
+    rc = gather_out(&v, 1, 0, out, count);
+    free(v.v);
+    return rc;
 }
 
 void oracle_free(void *p)

@@ -56,6 +56,11 @@ def _load():
         lib.pmsgen_uniform01.argtypes = [ctypes.c_void_p]
         lib.pmsgen_splitmix64.restype = ctypes.c_uint64
         lib.pmsgen_splitmix64.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+        lib.pmsgen_planted_alpha.restype = ctypes.c_int
+        lib.pmsgen_planted_alpha.argtypes = [
+            ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_char_p, ctypes.c_int, ctypes.c_char_p,
+            ctypes.c_char_p]
         lib.pmsgen_planted.restype = ctypes.c_int
         lib.pmsgen_planted.argtypes = [
             ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -119,6 +124,23 @@ def planted(seed: int, n: int, m: int, l: int, d: int) -> Instance:
     return Instance(seed=seed, n=n, m=m, l=l, d=d, seqs=seqs.raw[:n * m],
                     motif=motif.raw[:l], positions=list(pos),
                     mutated=[list(mut[i * d:(i + 1) * d]) for i in range(n)])
+
+
+PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"   # the 20 amino-acid letters
+
+
+def planted_alpha(seed: int, n: int, m: int, l: int, d: int,
+                  alphabet: bytes = PROTEIN) -> Instance:
+    """FM-model instance over an arbitrary alphabet (2..32 letters)."""
+    lib = _load()
+    seqs = ctypes.create_string_buffer(n * m)
+    motif = ctypes.create_string_buffer(max(l, 1))
+    rc = lib.pmsgen_planted_alpha(ctypes.c_uint64(seed), n, m, l, d,
+                                  bytes(alphabet), len(alphabet), seqs, motif)
+    if rc != 0:
+        raise ValueError("pmsgen_planted_alpha: bad sizes or alphabet")
+    return Instance(seed=seed, n=n, m=m, l=l, d=d, seqs=seqs.raw[:n * m],
+                    motif=motif.raw[:l])
 
 
 # ---------------------------------------------------------------------------

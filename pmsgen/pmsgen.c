@@ -165,6 +165,58 @@ pmsgen_rng *pmsgen_rng_new(uint64_t seed)
     return r;
 }
 
+/* The same FM-model planting over an alphabet of sigma letters (the bytes
+ * alpha[0..sigma-1], 2 <= sigma <= 32): background letters row-major, one
+ * bounded draw each; the motif (l draws); then per string a start position,
+ * d distinct positions (partial Fisher-Yates) and for each a letter among
+ * the sigma-1 others, (b + 1 + U{0..sigma-2}) mod sigma. */
+int pmsgen_planted_alpha(uint64_t seed, int n, int m, int l, int d,
+                         const char *alpha, int sigma, char *seqs,
+                         char *motif)
+{
+    if (n < 1 || m < 1 || l < 1 || l > m || d < 0 || d > l || !seqs ||
+        !alpha || sigma < 2 || sigma > 32)
+        return -1;
+    pmsgen_rng r;
+    pmsgen_seed(&r, seed);
+    size_t total = (size_t)n * (size_t)m;
+    for (size_t k = 0; k < total; k++)
+        seqs[k] = alpha[pmsgen_bounded(&r, (uint64_t)sigma)];
+    int *mb = (int *)malloc(sizeof(int) * (size_t)l);
+    int *idx = (int *)malloc(sizeof(int) * (size_t)l);
+    if (!mb || !idx) {
+        free(mb);
+        free(idx);
+        return -1;
+    }
+    for (int j = 0; j < l; j++)
+        mb[j] = (int)pmsgen_bounded(&r, (uint64_t)sigma);
+    if (motif)
+        for (int j = 0; j < l; j++)
+            motif[j] = alpha[mb[j]];
+    for (int i = 0; i < n; i++) {
+        int p = (int)pmsgen_bounded(&r, (uint64_t)(m - l + 1));
+        char *occ = seqs + (size_t)i * m + p;
+        for (int j = 0; j < l; j++) {
+            idx[j] = j;
+            occ[j] = alpha[mb[j]];
+        }
+        for (int t = 0; t < d; t++) {
+            int q = t + (int)pmsgen_bounded(&r, (uint64_t)(l - t));
+            int tmp = idx[t];
+            idx[t] = idx[q];
+            idx[q] = tmp;
+            int b = mb[idx[t]];
+            int nb = (b + 1 + (int)pmsgen_bounded(&r, (uint64_t)(sigma - 1))) %
+                     sigma;
+            occ[idx[t]] = alpha[nb];
+        }
+    }
+    free(mb);
+    free(idx);
+    return 0;
+}
+
 void pmsgen_rng_free(pmsgen_rng *r)
 {
     free(r);

@@ -3,7 +3,7 @@
 Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
 on inputs from the seeded generator; nothing here touches the GPU library.
 Run from the repository root:  python tests/golden/make_golden.py
-(add "quorum" to write only the quorum files)
+(add "quorum" or "protein" to write only those files)
 """
 import hashlib
 import os
@@ -73,9 +73,40 @@ def main_quorum():
         print(name, seed, q, len(q1))
 
 
+# other alphabets: the protein alphabet at (8,3), n = 20, m = 600 (S1 only:
+# the 20^8 space is beyond the brute force)
+PCASES = [(1, 8, 3)]
+
+
+def main_protein():
+    for seed, l, d in PCASES:
+        inst = pmsgen.planted_alpha(seed, 20, 600, l, d)
+        t0 = time.time()
+        got = oracle.s1(inst.seqs, pmsgen.PROTEIN, 20, 600, l, d)
+        plant = 0
+        for ch in inst.motif:
+            plant = plant * 20 + pmsgen.PROTEIN.index(ch)
+        path = os.path.join(HERE, "protein_%d_%d_seed%d.txt" % (l, d, seed))
+        with open(path, "w") as f:
+            f.write("# Exact (l,d)-motif set of one synthetic planted protein\n")
+            f.write("# instance, written by tests/golden/make_golden.py from the\n")
+            f.write("# CPU oracle S1 (codes in base 20 over the alphabet below).\n")
+            f.write("alphabet = %s\nseed = %d\n" % (pmsgen.PROTEIN.decode(), seed))
+            f.write("n = 20\nm = 600\nl = %d\nd = %d\n" % (l, d))
+            f.write("input_sha256 = %s\n" % hashlib.sha256(inst.seqs).hexdigest())
+            f.write("planted = %s\nplanted_code = %d\n" % (inst.motif.decode(), plant))
+            f.write("count = %d\n" % len(got))
+            f.write("motifs = %s\n" % ",".join(str(int(v)) for v in got))
+        print("protein", seed, l, d, len(got), "%.1fs" % (time.time() - t0))
+
+
 if __name__ == "__main__":
+    if len(sys.argv) > 1 and sys.argv[1] == "protein":
+        main_protein()
+        sys.exit(0)
     if len(sys.argv) > 1 and sys.argv[1] == "quorum":
         main_quorum()
     else:
         main()
         main_quorum()
+        main_protein()
