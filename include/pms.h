@@ -141,6 +141,32 @@ int pms_solve_quorum_device(pms_ctx *ctx, const uint8_t *d_seqs, int n,
                             int m, int l, int d, int q, void *stream,
                             uint64_t *d_out, size_t cap, size_t *count);
 
+/*
+ * Motifs over another alphabet (Sec. 1.2.5 states the problem for any
+ * alphabet; Table 3.1 sizes the spheres for any |Sigma|), e.g. the 20
+ * amino-acid letters. alphabet: sigma distinct bytes (2 <= sigma <= 32);
+ * the letter alphabet[i] has code i and a motif is reported as the base-sigma
+ * number sum_j code(M[j]) * sigma^(l-1-j) (first letter in the top digit,
+ * so numeric order is the alphabet's lexicographic order). seqs: n*m bytes
+ * of those letters, row-major. Runs the sample-driven filter (candidates
+ * from the spheres of s_1's l-mers, strings tested in order with early
+ * exit), then sorts and drops repeats on the device. Output as pms_solve.
+ * PMS_EBASE for a byte outside the alphabet; PMS_EINVAL for a bad shape, a
+ * bad alphabet, sigma^l beyond 64 bits or a sphere beyond 2^62 candidates
+ * (or 2^22 position sets). alphabet "ACGT" with sigma 4 is pms_solve.
+ */
+int pms_solve_alphabet(pms_ctx *ctx, const char *alphabet, int sigma,
+                       const char *seqs, int n, int m, int l, int d,
+                       const uint64_t **motifs, size_t *count);
+
+/* pms_solve_alphabet with input and output in device memory, as
+ * pms_solve_device (PMS_ENOMEM with *count = the size needed when cap is
+ * too small). */
+int pms_solve_alphabet_device(pms_ctx *ctx, const char *alphabet, int sigma,
+                              const uint8_t *d_seqs, int n, int m, int l,
+                              int d, void *stream, uint64_t *d_out,
+                              size_t cap, size_t *count);
+
 /* One instance of a batch or a serving request. seqs: n*m host bytes. */
 typedef struct {
     const char *seqs;

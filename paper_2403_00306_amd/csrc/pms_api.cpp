@@ -732,6 +732,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->n_cu = prop.multiProcessorCount;
     c->tiled_bpc = tiled_blocks_per_cu();
     c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
+    c->alpha_bpc = alpha_blocks_per_cu();
     c->filter_bpc = filter_blocks_per_cu();
     size_t freeb = 0, totb = 0;
     if (hipMemGetInfo(&freeb, &totb) != hipSuccess) {
@@ -806,7 +807,7 @@ void pms_destroy(pms_ctx *c)
         hipGraphDestroy(c->b_graph_def);
     }
     for (DevBuf *b : {&c->arena, &c->out, &c->masks, &c->hc_ref, &c->sort_scr,
-                      &c->bitset, &c->alive, &c->b_arena})
+                      &c->bitset, &c->alive, &c->b_arena, &c->aux})
         c->release(*b);
     if (c->tables_mem)
         hipFree(c->tables_mem);

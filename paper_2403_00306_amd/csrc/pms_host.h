@@ -78,7 +78,8 @@ struct pms_ctx {
     std::string err;
     std::string tune_path;
     hipStream_t stream = nullptr;
-    int n_cu = 0, tiled_bpc = 1, filter_bpc = 1, tiled_q_bpc = 1;
+    int n_cu = 0, tiled_bpc = 1, filter_bpc = 1, tiled_q_bpc = 1,
+        alpha_bpc = 1;
     size_t budget = 0;
     std::atomic<size_t> held{0};
 
@@ -86,6 +87,7 @@ struct pms_ctx {
     pms::Tables tb{};
 
     pms::DevBuf arena, out, masks, hc_ref, sort_scr, bitset, alive;
+    pms::DevBuf aux;              // any-alphabet path: heap, repeat removal
     int masks_l = -1, masks_d = -1;
     uint64_t masks_nb = 0;
     std::vector<uint64_t> host_out;

@@ -130,6 +130,37 @@ hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
                         int nitems, uint64_t chunk, unsigned int *d_next,
                         Tables tb, TileStats *stats, int grid, hipStream_t st);
 int tiled_blocks_per_cu();
+// Any-alphabet sample-driven filter (k_alpha.hip).
+struct AlphaJob {
+    const uint8_t *letters;      // n*m letter codes (index in the alphabet)
+    const uint32_t *planes;      // n*L l-mers, 8 words each: bit planes 0..4
+    const uint32_t *posset;      // position sets (bitmasks) by weight k,
+    const uint64_t *posoff;      //   weight k starting at posoff[k]
+    const uint64_t *cum;         // first flat sphere index of weight k
+    const uint64_t *powr;        // (sigma-1)^k
+    uint64_t nb;                 // sphere size n_B(l, d) over sigma letters
+    uint64_t *heap;              // survivors (unordered, repeats possible)
+    unsigned long long *heap_top;
+    unsigned long long heap_cap;
+    int n, m, l, d, L, sigma;
+};
+hipError_t launch_alpha_index(const uint8_t *seqs, const uint8_t *map, int n,
+                              int m, int l, int P, uint8_t *letters,
+                              uint32_t *planes, unsigned long long *bad,
+                              hipStream_t st);
+hipError_t launch_alpha_filter(const AlphaJob &J, unsigned int *next,
+                               int grid, hipStream_t st);
+// Sorted a[0..n): flag[i] = 1 where a value starts, pos = exclusive scan
+// of flag (n+1 entries, pos[n] = number of distinct values); then the
+// distinct values to out[0..pos[n]) (out must not overlap a).
+hipError_t launch_unique_count(const uint64_t *a, uint64_t n, uint32_t *flag,
+                               uint64_t *pos, void *scan_scratch,
+                               hipStream_t st);
+hipError_t launch_unique_scatter(const uint64_t *a, uint64_t n,
+                                 const uint32_t *flag, const uint64_t *pos,
+                                 uint64_t *out, hipStream_t st);
+int alpha_blocks_per_cu();
+
 // Quorum variant of launch_tiled (instances with q < n, tile suffix at
 // most kQuorumMaxSuffix, n - q at most kQuorumMaxMiss).
 hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,
