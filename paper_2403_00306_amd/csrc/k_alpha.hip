@@ -62,7 +62,11 @@ k_alpha_filter(AlphaJob J, unsigned int *next, unsigned long long nitems)
 {
     __shared__ uint8_t xl[kMaxL];
     __shared__ unsigned long long s_item;
+    __shared__ unsigned long long s_hc;
     const int tid = threadIdx.x;
+    unsigned long long hc = 0;   // this thread's canonical test count
+    if (tid == 0)
+        s_hc = 0;
     const uint64_t per_ref = (J.nb + kAlphaChunk - 1) / kAlphaChunk;
     for (;;) {
         __syncthreads();
@@ -122,8 +126,10 @@ k_alpha_filter(AlphaJob J, unsigned int *next, unsigned long long nitems)
                 J.planes + (size_t)i * J.L * kAlphaStride);
             bool hit[kAlphaPer];
 #pragma unroll
-            for (int u = 0; u < kAlphaPer; u++)
+            for (int u = 0; u < kAlphaPer; u++) {
                 hit[u] = !live[u];
+                hc += live[u] ? (unsigned long long)J.L : 0ull;
+            }
             for (int y0 = 0; y0 < J.L; y0 += 8) {
                 const int y1 = min(y0 + 8, J.L);
                 for (int y = y0; y < y1; y++) {
@@ -167,6 +173,11 @@ k_alpha_filter(AlphaJob J, unsigned int *next, unsigned long long nitems)
                 J.heap[at] = code;
         }
     }
+    if (hc)
+        atomicAdd(&s_hc, hc);
+    __syncthreads();
+    if (tid == 0 && s_hc)
+        atomicAdd(J.hcanon, s_hc);
 }
 
 // 1 where a sorted array starts a new value.

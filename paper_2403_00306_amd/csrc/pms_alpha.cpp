@@ -146,7 +146,7 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
         const size_t o_bad = take(8);
         const size_t o_pos = take(P.posset.size() * 4);
         const size_t o_tab = take(3 * (kMaxL + 2) * 8);
-        const size_t o_cnt = take(16);   // next item, heap top
+        const size_t o_cnt = take(24);   // next item, heap top, tests
         if ((rc = c->alloc(c->arena, off)))
             return rc;
         // aux: heap, flags, positions, scan scratch
@@ -188,7 +188,7 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
         HIPCHK(c, hipMemcpyAsync(tab, t.data(), t.size() * 8,
                                  hipMemcpyHostToDevice, st));
         HIPCHK(c, launch_fill_u64(bad, 1, ~0ull, st));
-        HIPCHK(c, launch_fill_u64((unsigned long long *)next, 2, 0, st));
+        HIPCHK(c, launch_fill_u64((unsigned long long *)next, 3, 0, st));
         HIPCHK(c, launch_alpha_index(seqs, (const uint8_t *)(base + o_map), n,
                                      m, l, planes, (uint8_t *)(base + o_let),
                                      (uint32_t *)(base + o_pl), bad, st));
@@ -204,6 +204,7 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
         J.heap = (uint64_t *)(abase + a_heap);
         J.heap_top = top;
         J.heap_cap = heap_cap;
+        J.hcanon = (unsigned long long *)(base + o_cnt + 16);
         J.n = n;
         J.m = m;
         J.l = l;
@@ -217,7 +218,10 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
         unsigned long long *hp = c->pinned;
         HIPCHK(c, hipMemcpyAsync(hp, top, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipMemcpyAsync(hp + 1, bad, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(hp + 2, J.hcanon, 8, hipMemcpyDeviceToHost,
+                                 st));
         HIPCHK(c, hipStreamSynchronize(st));
+        S.hcanon = hp[2];
         if (hp[1] != ~0ull)
             return c->fail(PMS_EBASE, "byte not in the alphabet in string "
                            "%llu at offset %llu", hp[1] / m, hp[1] % m);

@@ -142,6 +142,8 @@ struct AlphaJob {
     uint64_t *heap;              // survivors (unordered, repeats possible)
     unsigned long long *heap_top;
     unsigned long long heap_cap;
+    unsigned long long *hcanon;  // canonical Hamming tests (L per string
+                                 //   examined, first failing one included)
     int n, m, l, d, L, sigma;
 };
 hipError_t launch_alpha_index(const uint8_t *seqs, const uint8_t *map, int n,

@@ -75,6 +75,16 @@ def test_alpha_dna_letter_order(ctx):
     assert (got == want).all()
 
 
+def test_alpha_canonical_test_count(ctx):
+    # relabelling letters maps spheres to spheres and strings to strings, so
+    # DNA in another letter order has the DNA oracle's H_canon exactly
+    inst = pmsgen.plain("pms_9_2", 2)
+    seqs = inst.seqs[:10 * 200]
+    ctx.solve_alphabet(b"GATC", seqs, 10, 200, 8, 2)
+    _, h = oracle.o1(seqs, 10, 200, 8, 2)
+    assert ctx.stats()["hcanon"] == h
+
+
 def test_alpha_protein_full_size_stored(ctx):
     kv = {}
     for line in open(os.path.join(GOLDEN, "protein_8_3_seed1.txt")):
