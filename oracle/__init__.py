@@ -57,6 +57,11 @@ def _load():
                 ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                 ctypes.c_int, ctypes.c_int, ctypes.c_int,
                 ctypes.POINTER(u64p), ctypes.POINTER(ctypes.c_size_t)]
+        lib.oracle_p1.restype = ctypes.c_int
+        lib.oracle_p1.argtypes = [
+            ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p),
+            ctypes.POINTER(ctypes.c_size_t), u64p]
         lib.oracle_s1.restype = ctypes.c_int
         lib.oracle_s1.argtypes = [
             ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, ctypes.c_int,
@@ -183,6 +188,20 @@ def q0(seqs, n, m, l, d, q, threads=0) -> np.ndarray:
     """(l,d,q)-motifs by brute force over all 4^l codes."""
     return _quorum(_load().oracle_q0, "oracle_q0", seqs, n, m, l, d, q,
                    threads)
+
+
+def p1(seqs, n, m, l, d, threads=0):
+    """Pair-based (Observation 3.3): (motifs, number of candidates)."""
+    buf = _seq_bytes(seqs)
+    assert len(buf) == n * m
+    out = ctypes.POINTER(ctypes.c_uint64)()
+    count = ctypes.c_size_t(0)
+    nc = ctypes.c_uint64(0)
+    rc = _load().oracle_p1(buf, n, m, l, d, threads, ctypes.byref(out),
+                           ctypes.byref(count), ctypes.byref(nc))
+    if rc != OR_OK:
+        raise OracleError(rc, "oracle_p1")
+    return _take(out, count.value), int(nc.value)
 
 
 def s1(seqs, alphabet: bytes, n, m, l, d, threads=0) -> np.ndarray:

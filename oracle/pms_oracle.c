@@ -44,6 +44,12 @@
  *      character with every l-mer of every string, kept when at least q
  *      strings have a d-neighbour.
  *
+ * Pair-based candidates (Observation 3.3 with q = n): a motif M has an
+ * l-mer x in s_1 and an l-mer y in s_2 within distance d of it, so
+ * d_H(x,y) <= 2d and M lies in B(x,d) ∩ B(y,d). P1 takes every such pair,
+ * walks T_d(x), keeps the candidates within d of y (the intersection) and
+ * tests them against s_3..s_n; repeats (one motif, several pairs) dropped.
+ *
  * Other alphabets (Sec. 1.2.5 defines the problem over any alphabet Sigma;
  * Table 3.1 gives n_B for any |Sigma|): S1 and S0 are O1 and O0 over an
  * alphabet of sigma letters given by the caller (letter code = its index
@@ -843,6 +849,135 @@ int oracle_hit_count(const char *seqs, int n, int m, int l, int d,
         hits += ok;
     }
     return hits;
+}
+
+/* ---- P1: pair-based candidates (Observation 3.3) ---------------------- */
+
+typedef struct {
+    const uint64_t *codes;   /* n rows of L packed codes */
+    const unsigned char *bases;
+    int n, L, l, d, nthreads, tid;
+    vec64 out;
+    uint64_t ncand;          /* candidates: sum of |B(x,d) ∩ B(y,d)| */
+} p1_job;
+
+/* strings s_3..s_n in order, stop at the first without a d-neighbour */
+static int p1_test(const p1_job *J, uint64_t cand)
+{
+    for (int i = 2; i < J->n; i++) {
+        const uint64_t *row = J->codes + (size_t)i * J->L;
+        int hit = 0;
+        for (int j = 0; j < J->L && !hit; j++)
+            hit = hamming_packed(cand, row[j]) <= J->d;
+        if (!hit)
+            return 0;
+    }
+    return 1;
+}
+
+/* T_d(x), keeping the nodes within distance d of y */
+static void p1_ball(p1_job *J, const unsigned char *x, uint64_t y,
+                    uint64_t cand, int from, int budget)
+{
+    if (hamming_packed(cand, y) <= J->d) {
+        J->ncand++;
+        if (p1_test(J, cand))
+            vpush(&J->out, cand);
+    }
+    if (budget == 0)
+        return;
+    for (int p = from; p < J->l; p++) {
+        int shift = 2 * (J->l - 1 - p);
+        for (int b = 0; b < 4; b++) {
+            if (b == x[p])
+                continue;
+            p1_ball(J, x, y, cand ^ ((uint64_t)(x[p] ^ b) << shift), p + 1,
+                    budget - 1);
+        }
+    }
+}
+
+static void *p1_worker(void *arg)
+{
+    p1_job *J = (p1_job *)arg;
+    int lo = (int)((long long)J->L * J->tid / J->nthreads);
+    int hi = (int)((long long)J->L * (J->tid + 1) / J->nthreads);
+    const uint64_t *row2 = J->codes + J->L;   /* s_2 */
+    for (int j = lo; j < hi; j++) {
+        const unsigned char *x = J->bases + j;
+        const uint64_t xc = J->codes[j];
+        for (int k = 0; k < J->L; k++)
+            if (hamming_packed(xc, row2[k]) <= 2 * J->d)
+                p1_ball(J, x, row2[k], xc, 0, J->d);
+    }
+    return NULL;
+}
+
+/* P1: the (l,d)-motifs from pair intersections (needs n >= 2). *ncand gets
+ * the number of candidates, sum over pairs of |B(x,d) ∩ B(y,d)|. */
+int oracle_p1(const char *seqs, int n, int m, int l, int d, int nthreads,
+              uint64_t **out, size_t *count, uint64_t *ncand)
+{
+    int rc = check_args(n, m, l, d);
+    if (rc)
+        return rc;
+    if (n < 2)
+        return OR_EINVAL;
+    int L = m - l + 1;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * L);
+    int T = pick_threads(nthreads);
+    if (T > L)
+        T = L;
+    p1_job *jobs = (p1_job *)calloc((size_t)T, sizeof(p1_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    vec64 *vs = (vec64 *)calloc((size_t)T, sizeof(vec64));
+    if (!bases || !codes || !jobs || !th || !vs) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    if (decode(seqs, total, bases) >= 0) {
+        rc = OR_EBASE;
+        goto done;
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < L; j++)
+            codes[(size_t)i * L + j] = lmer_code(bases + (size_t)i * m + j, l);
+    for (int t = 0; t < T; t++) {
+        p1_job *J = &jobs[t];
+        J->codes = codes;
+        J->bases = bases;
+        J->n = n;
+        J->L = L;
+        J->l = l;
+        J->d = d;
+        J->nthreads = T;
+        J->tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, p1_worker, &jobs[t]);
+    p1_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    uint64_t nc = 0;
+    for (int t = 0; t < T; t++) {
+        vs[t] = jobs[t].out;
+        nc += jobs[t].ncand;
+    }
+    rc = gather_out(vs, T, 1, out, count);
+    if (!rc && ncand)
+        *ncand = nc;
+done:
+    if (jobs)
+        for (int t = 0; t < T; t++)
+            free(jobs[t].out.v);
+    free(vs);
+    free(jobs);
+    free(th);
+    free(bases);
+    free(codes);
+    return rc;
 }
 
 /* ---- any alphabet: S1 (sample-driven) and S0 (brute force) ------------- */
