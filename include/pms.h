@@ -60,10 +60,15 @@ enum {
                              of the 4^l space resident in device memory,
                              one pass per string ANDs in the union of the
                              d-spheres of its l-mers (needs 4^l/8 bytes) */
-    PMS_PATH_TILED = 3    /* pattern-driven, tiled: the 4^l space split into
+    PMS_PATH_TILED = 3,   /* pattern-driven, tiled: the 4^l space split into
                              tiles held on chip; each tile ANDs the strings'
                              sphere unions until few codes are left, then
                              filters those by Hamming tests */
+    PMS_PATH_PAIR = 4     /* sample-driven from pairs (Observation 3.3):
+                             candidates from B(x,d) ∩ B(y,d) for x in s_1,
+                             y in s_2 with d_H(x,y) <= 2d, filtered against
+                             s_3..s_n; never chosen by AUTO; needs n >= 2
+                             and 2d <= 20 */
 };
 
 typedef struct pms_ctx pms_ctx;
@@ -241,9 +246,13 @@ typedef struct {
     uint64_t tiles;           /* tiled/bitset: tiles processed */
     uint64_t tile_passes;     /* tiled/bitset: (tile, string) passes run */
     uint64_t marks;           /* tiled/bitset: 64-bit sphere-word ORs */
-    uint64_t filter_tests;    /* tiled: Hamming tests of the filter stage */
+    uint64_t filter_tests;    /* tiled: Hamming tests of the filter stage;
+                                 pair path: tests against s_3..s_n (L per
+                                 string examined) */
     uint64_t bytes_main;      /* bitset path: device bytes read+written */
     uint64_t retries;         /* output-capacity retries */
+    uint64_t pairs;           /* pair path: pairs (x, y) with d_H <= 2d */
+    uint64_t candidates;      /* pair path: sum of |B(x,d) ∩ B(y,d)| */
 } pms_stats;
 
 int pms_last_stats(const pms_ctx *ctx, pms_stats *out);

@@ -19,8 +19,9 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pms.h")
 
 PMS_OK, PMS_PENDING = 0, 1
 PMS_EINVAL, PMS_EBASE, PMS_ENOMEM, PMS_EDEVICE, PMS_EBUSY = -1, -2, -3, -4, -5
-PATH_AUTO, PATH_FILTER, PATH_BITSET, PATH_TILED = 0, 1, 2, 3
-PATH_NAMES = {PATH_FILTER: "filter", PATH_BITSET: "bitset", PATH_TILED: "tiled"}
+PATH_AUTO, PATH_FILTER, PATH_BITSET, PATH_TILED, PATH_PAIR = 0, 1, 2, 3, 4
+PATH_NAMES = {PATH_FILTER: "filter", PATH_BITSET: "bitset", PATH_TILED: "tiled",
+              PATH_PAIR: "pair"}
 
 
 class PmsError(RuntimeError):
@@ -59,7 +60,8 @@ class Stats(ctypes.Structure):
                 ("hcanon", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
                 ("tile_passes", ctypes.c_uint64), ("marks", ctypes.c_uint64),
                 ("filter_tests", ctypes.c_uint64),
-                ("bytes_main", ctypes.c_uint64), ("retries", ctypes.c_uint64)]
+                ("bytes_main", ctypes.c_uint64), ("retries", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64), ("candidates", ctypes.c_uint64)]
 
 
 class ServeStats(ctypes.Structure):

@@ -13,8 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpms.so")
 SOURCES = ["k_index.hip", "k_tiles.hip", "k_filter.hip", "k_scan.hip",
-           "k_alpha.hip", "pms_api.cpp", "pms_batch.cpp", "pms_serve.cpp",
-           "pms_tune.cpp", "pms_alpha.cpp"]
+           "k_alpha.hip", "k_pair.hip", "pms_api.cpp", "pms_batch.cpp",
+           "pms_serve.cpp", "pms_tune.cpp", "pms_alpha.cpp", "pms_pair.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-result",

@@ -275,7 +275,7 @@ Plan pms_ctx::plan(int n, int m, int l, int d, int forced)
     p.ntiles = (l >= 3 && p.s >= 3) ? pow4(l - p.s) : 0;
     cost_model(n, m, l, d, p.s, p.surv_t, p.cost_filter, p.cost_tiled);
     if (forced == PMS_PATH_FILTER || forced == PMS_PATH_TILED ||
-        forced == PMS_PATH_BITSET)
+        forced == PMS_PATH_BITSET || forced == PMS_PATH_PAIR)
         p.path = forced;
     else
         p.path = (p.cost_tiled < p.cost_filter) ? PMS_PATH_TILED
@@ -285,7 +285,7 @@ Plan pms_ctx::plan(int n, int m, int l, int d, int forced)
     if ((p.path == PMS_PATH_TILED || p.path == PMS_PATH_BITSET) &&
         (l < 3 || p.s < 3 || l - p.s > kMaxTilePrefix))
         p.path = PMS_PATH_FILTER;
-    if (p.path == PMS_PATH_FILTER)
+    if (p.path == PMS_PATH_FILTER || p.path == PMS_PATH_PAIR)
         p.ntiles = 0;
     return p;
 }
@@ -381,7 +381,8 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         if (n - q > kQuorumMaxMiss)
             return c->fail(PMS_EINVAL, "quorum: n-q=%d above %d", n - q,
                            kQuorumMaxMiss);
-        if (forced_path == PMS_PATH_FILTER || forced_path == PMS_PATH_BITSET)
+        if (forced_path == PMS_PATH_FILTER || forced_path == PMS_PATH_BITSET ||
+            forced_path == PMS_PATH_PAIR)
             return c->fail(PMS_EINVAL, "quorum (q<n) runs the tiled path "
                            "only");
         forced_path = PMS_PATH_TILED;
@@ -406,7 +407,8 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
     if (P.path == PMS_PATH_BITSET && (l - 3 > 28 || pow4(l - 3) * 8 >
                                                         c->budget))
         return c->fail(PMS_ENOMEM, "bitset path needs 4^%d/8 bytes", l);
-    const auto shape_key = std::make_tuple(n, m, l, d, quorum ? q : n);
+    const auto shape_key =
+        std::make_tuple(n, m, l, d, (quorum ? q : n) * 8 + P.path);
     if (P.path != PMS_PATH_BITSET) {
         auto hn = c->heap_need.find(shape_key);
         if (hn != c->heap_need.end())
@@ -513,6 +515,56 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                                          hipMemcpyDeviceToDevice, st));
                 HIPCHK(c, launch_sort_u64(dst, total, 2 * l, c->sort_scr.p,
                                           st));
+            }
+            HIPCHK(c, hipEventRecord(c->ev[3], st));
+            res->count = total;
+        } else if (P.path == PMS_PATH_PAIR) {
+            uint64_t found = 0;
+            if ((rc = pair_run(c, I, st, &found, S)))
+                return rc;
+            HIPCHK(c, hipEventRecord(c->ev[2], st));
+            HIPCHK(c, hipMemcpyAsync(hp + 2, I.bad, 8, hipMemcpyDeviceToHost,
+                                     st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            if (hp[2] != ~0ull)
+                return c->fail(PMS_EBASE, "bad base in string %llu at offset "
+                               "%llu", hp[2] / m, hp[2] % m);
+            if (found > heap_cap) {
+                heap_cap = found + 1024;
+                S.retries++;
+                continue;
+            }
+            c->heap_need[shape_key] = found + 1024;
+            // sort, then drop repeats (one motif from several pairs)
+            uint64_t total = 0;
+            if (found) {
+                if ((rc = c->alloc(c->sort_scr, sort_scratch_bytes(found))))
+                    return rc;
+                HIPCHK(c, launch_sort_u64(I.heap, found, 2 * l, c->sort_scr.p,
+                                          st));
+                const size_t o_pos = align_up(found * 4);
+                const size_t o_scan = o_pos + align_up((found + 1) * 8);
+                if ((rc = c->alloc(c->aux, o_scan +
+                                               scan_scratch_bytes(found))))
+                    return rc;
+                char *ab = (char *)c->aux.p;
+                HIPCHK(c, launch_unique_count(I.heap, found, (uint32_t *)ab,
+                                              (uint64_t *)(ab + o_pos),
+                                              ab + o_scan, st));
+                HIPCHK(c, hipMemcpyAsync(hp, (uint64_t *)(ab + o_pos) + found,
+                                         8, hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipStreamSynchronize(st));
+                total = hp[0];
+                if (total > dst_cap) {
+                    res->count = total;
+                    return c->fail(PMS_ENOMEM, "output capacity %llu < %llu",
+                                   (unsigned long long)dst_cap,
+                                   (unsigned long long)total);
+                }
+                HIPCHK(c, launch_unique_scatter(I.heap, found,
+                                                (const uint32_t *)ab,
+                                                (const uint64_t *)(ab + o_pos),
+                                                dst, st));
             }
             HIPCHK(c, hipEventRecord(c->ev[3], st));
             res->count = total;
@@ -638,7 +690,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                     h += v;
             }
             S.hcanon = h;
-        } else {
+        } else if (P.path != PMS_PATH_PAIR) {
             S.tiles = (P.path == PMS_PATH_TILED) ? ts.tiles : ntiles;
             S.tile_passes = ts.passes;
             S.marks = ts.marks;
@@ -709,7 +761,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
         g_create_error = "bad device ordinal";
         return PMS_EINVAL;
     }
-    if (o.path < 0 || o.path > PMS_PATH_TILED || o.serve_slots < 0 ||
+    if (o.path < 0 || o.path > PMS_PATH_PAIR || o.serve_slots < 0 ||
         o.serve_queue < 0) {
         g_create_error = "bad option value";
         return PMS_EINVAL;
@@ -733,6 +785,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->tiled_bpc = tiled_blocks_per_cu();
     c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
     c->alpha_bpc = alpha_blocks_per_cu();
+    c->pair_bpc = pair_blocks_per_cu();
     c->filter_bpc = filter_blocks_per_cu();
     size_t freeb = 0, totb = 0;
     if (hipMemGetInfo(&freeb, &totb) != hipSuccess) {

@@ -79,7 +79,7 @@ struct pms_ctx {
     std::string tune_path;
     hipStream_t stream = nullptr;
     int n_cu = 0, tiled_bpc = 1, filter_bpc = 1, tiled_q_bpc = 1,
-        alpha_bpc = 1;
+        alpha_bpc = 1, pair_bpc = 1;
     size_t budget = 0;
     std::atomic<size_t> held{0};
 
@@ -141,6 +141,11 @@ namespace pms {
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,
                size_t cap_ext, int forced_path, SolveOut *res, int q = 0);
+// Pair path: lists compatible pairs and filters their candidates into
+// I.heap (index already built on st); *found = survivors, possibly more
+// than I.heap_cap (then nothing beyond it was written).
+int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
+             pms_stats &S);
 void serve_shutdown(pms_ctx *c);
 void load_tune_cache(pms_ctx *c);
 }  // namespace pms

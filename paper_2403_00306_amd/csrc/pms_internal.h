@@ -163,6 +163,35 @@ hipError_t launch_unique_scatter(const uint64_t *a, uint64_t n,
                                  uint64_t *out, hipStream_t st);
 int alpha_blocks_per_cu();
 
+// Pair-based candidates (k_pair.hip).
+struct PairTuple {
+    uint64_t first;              // first flat index of this tuple for its D
+    uint8_t a, b, c, e;          // letters from x / from y / other on the
+    uint32_t pad;                //   differing positions; changed agreeing
+};
+struct PairJob {
+    const uint2 *planes;         // the instance's l-mer planes (row 0 = s_1)
+    const uint64_t *nD;          // |B(x,d) ∩ B(y,d)| by D = d_H(x,y)
+    const PairTuple *tup;        // tuples of every D, D's at tup_off[D]
+    const int *tup_off;
+    const uint64_t *pow3, *fact, *binom;   // binom[n*(kMaxL+1)+k]
+    uint2 *pairs;                // compatible pairs (index in s_1, in s_2)
+    uint32_t *chunks;            // work items per pair
+    unsigned long long *npairs, *ncand, *next, *tests;
+    unsigned long long pairs_cap;
+    const uint64_t *item_pos;    // exclusive scan of chunks (npairs+1)
+    uint64_t *heap;              // survivors (unordered, repeats possible)
+    unsigned long long *heap_top;
+    unsigned long long heap_cap;
+    int n, L, l, d;
+};
+hipError_t launch_pair_list(const PairJob &J, hipStream_t st);
+hipError_t launch_pair_filter(const PairJob &J, unsigned long long nitems,
+                              unsigned long long npairs, int grid,
+                              hipStream_t st);
+int pair_chunk();
+int pair_blocks_per_cu();
+
 // Quorum variant of launch_tiled (instances with q < n, tile suffix at
 // most kQuorumMaxSuffix, n - q at most kQuorumMaxMiss).
 hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,

@@ -1,0 +1,171 @@
+// pms_pair.cpp -- host side of the pair-based path (PMS_PATH_PAIR).
+//
+// Observation 3.3 with q = n: every motif lies in B(x,d) ∩ B(y,d) for an
+// l-mer x of s_1 and an l-mer y of s_2 with d_H(x,y) <= 2d. The host builds
+// the counting tables of those intersections (they depend on D = d_H(x,y)
+// only), then the device lists the compatible pairs, scans their work-item
+// counts and filters every pair's candidates against s_3..s_n.
+#include "pms_host.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace pms {
+
+int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
+             pms_stats &S)
+{
+    const int n = I.n, L = I.L, l = I.l, d = I.d;
+    if (n < 2)
+        return c->fail(PMS_EINVAL, "pair path needs n >= 2 strings");
+    if (2 * d > 20)
+        return c->fail(PMS_EINVAL, "pair path needs 2d <= 20 (d=%d)", d);
+    const uint64_t LL = (uint64_t)L * (uint64_t)L;
+    if (LL > (1ull << 28))
+        return c->fail(PMS_EINVAL, "pair path: (m-l+1)^2 = %llu pairs above "
+                       "2^28", (unsigned long long)LL);
+
+    // counting tables: factorials, powers of 3, binomials, and per D the
+    // tuples (a, b, c, e) with their sizes
+    std::vector<uint64_t> fact(21, 1), pow3(kMaxL + 1, 1),
+        binom((kMaxL + 1) * (kMaxL + 1), 0);
+    for (int i = 1; i <= 20; i++)
+        fact[i] = fact[i - 1] * (uint64_t)i;
+    for (int i = 1; i <= kMaxL; i++)
+        pow3[i] = pow3[i - 1] * 3;
+    for (int a = 0; a <= kMaxL; a++) {
+        binom[a * (kMaxL + 1)] = 1;
+        for (int b = 1; b <= a; b++)
+            binom[a * (kMaxL + 1) + b] = binom[(a - 1) * (kMaxL + 1) + b - 1] +
+                                         (b <= a - 1
+                                              ? binom[(a - 1) * (kMaxL + 1) + b]
+                                              : 0);
+    }
+    std::vector<PairTuple> tup;
+    std::vector<int> tup_off(2 * d + 2 + 1, 0);
+    std::vector<uint64_t> nD(2 * d + 2, 0);
+    for (int D = 0; D <= 2 * d && D <= l; D++) {
+        tup_off[D] = (int)tup.size();
+        uint64_t acc = 0;
+        for (int a = 0; a <= D; a++)
+            for (int b = 0; a + b <= D; b++) {
+                const int cc = D - a - b;
+                for (int e = 0; e <= l - D; e++) {
+                    if (b + cc + e > d || a + cc + e > d)
+                        continue;
+                    const unsigned __int128 cnt =
+                        (unsigned __int128)(fact[D] /
+                                            (fact[a] * fact[b] * fact[cc])) *
+                        (1ull << cc) * binom[(l - D) * (kMaxL + 1) + e] *
+                        pow3[e];
+                    PairTuple t{};
+                    t.first = acc;
+                    t.a = (uint8_t)a;
+                    t.b = (uint8_t)b;
+                    t.c = (uint8_t)cc;
+                    t.e = (uint8_t)e;
+                    tup.push_back(t);
+                    // work items per pair are 32-bit counts of 1024
+                    if (cnt > ((unsigned __int128)1 << 40) ||
+                        acc + (uint64_t)cnt > (1ull << 40))
+                        return c->fail(PMS_EINVAL, "pair path: intersections "
+                                       "of (%d,%d) too large", l, d);
+                    acc += (uint64_t)cnt;
+                }
+            }
+        nD[D] = acc;
+    }
+    for (int D = std::min(2 * d, l) + 1; D <= 2 * d + 2; D++)
+        tup_off[D] = (int)tup.size();
+
+    // device layout (the aux buffer): tables, counters, pair arrays
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t o_nD = take(nD.size() * 8);
+    const size_t o_tup = take(std::max<size_t>(tup.size(), 1) *
+                              sizeof(PairTuple));
+    const size_t o_toff = take(tup_off.size() * 4);
+    const size_t o_p3 = take(pow3.size() * 8);
+    const size_t o_fact = take(fact.size() * 8);
+    const size_t o_bin = take(binom.size() * 8);
+    const size_t o_cnt = take(4 * 8);
+    const size_t o_pairs = take(LL * 8);
+    const size_t o_chunks = take(LL * 4);
+    const size_t o_pos = take((LL + 1) * 8);
+    const size_t o_scan = take(scan_scratch_bytes(LL));
+    int rc = c->alloc(c->aux, off);
+    if (rc)
+        return rc;
+    char *b = (char *)c->aux.p;
+    HIPCHK(c, hipMemcpyAsync(b + o_nD, nD.data(), nD.size() * 8,
+                             hipMemcpyHostToDevice, st));
+    if (!tup.empty())
+        HIPCHK(c, hipMemcpyAsync(b + o_tup, tup.data(),
+                                 tup.size() * sizeof(PairTuple),
+                                 hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b + o_toff, tup_off.data(), tup_off.size() * 4,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b + o_p3, pow3.data(), pow3.size() * 8,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b + o_fact, fact.data(), fact.size() * 8,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b + o_bin, binom.data(), binom.size() * 8,
+                             hipMemcpyHostToDevice, st));
+    unsigned long long *cnt = (unsigned long long *)(b + o_cnt);
+    HIPCHK(c, launch_fill_u64(cnt, 4, 0, st));
+
+    PairJob J;
+    J.planes = I.planes;
+    J.nD = (const uint64_t *)(b + o_nD);
+    J.tup = (const PairTuple *)(b + o_tup);
+    J.tup_off = (const int *)(b + o_toff);
+    J.pow3 = (const uint64_t *)(b + o_p3);
+    J.fact = (const uint64_t *)(b + o_fact);
+    J.binom = (const uint64_t *)(b + o_bin);
+    J.pairs = (uint2 *)(b + o_pairs);
+    J.chunks = (uint32_t *)(b + o_chunks);
+    J.npairs = cnt;
+    J.ncand = cnt + 1;
+    J.next = cnt + 2;
+    J.tests = cnt + 3;
+    J.pairs_cap = LL;
+    J.item_pos = (const uint64_t *)(b + o_pos);
+    J.heap = I.heap;
+    J.heap_top = I.heap_top;
+    J.heap_cap = I.heap_cap;
+    J.n = n;
+    J.L = L;
+    J.l = l;
+    J.d = d;
+    HIPCHK(c, launch_pair_list(J, st));
+    unsigned long long *hp = c->pinned + 4;
+    HIPCHK(c, hipMemcpyAsync(hp, cnt, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const unsigned long long npairs = hp[0], ncand = hp[1];
+    unsigned long long nitems = 0;
+    if (npairs) {
+        HIPCHK(c, launch_scan_u32(J.chunks, npairs, (uint64_t *)J.item_pos,
+                                  b + o_scan, st));
+        HIPCHK(c, hipMemcpyAsync(hp, J.item_pos + npairs, 8,
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        nitems = hp[0];
+    }
+    HIPCHK(c, launch_pair_filter(J, nitems, npairs,
+                                 std::max(1, c->n_cu * c->pair_bpc), st));
+    HIPCHK(c, hipMemcpyAsync(hp, I.heap_top, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(hp + 1, J.tests, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    *found = hp[0];
+    S.pairs = npairs;
+    S.candidates = ncand;
+    S.filter_tests = hp[1];
+    S.main_launches = 2;
+    return PMS_OK;
+}
+
+}  // namespace pms
