@@ -45,12 +45,6 @@ k_pair_list(PairJob J)
 
 typedef __attribute__((address_space(4))) const unsigned long long c_u64;
 
-__device__ __forceinline__ uint64_t multinom(const uint64_t *fact, int n,
-                                             int a, int b, int c)
-{
-    return fact[n] / (fact[a] * fact[b] * fact[c]);
-}
-
 __device__ __forceinline__ void set_letter(uint32_t &hi, uint32_t &lo, int p,
                                            uint32_t v)
 {
@@ -58,15 +52,114 @@ __device__ __forceinline__ void set_letter(uint32_t &hi, uint32_t &lo, int p,
     lo = (lo & ~(1u << p)) | ((v & 1u) << p);
 }
 
+__device__ __forceinline__ uint32_t multi_at(const uint32_t *M, int r, int a,
+                                             int b)
+{
+    return M[(r * (kPairMaxD + 1) + a) * (kPairMaxD + 1) + b];
+}
+
+// Test the candidates (planes ch/cl, kPairPer per thread) against one
+// string's l-mers; on return live[u] holds "has a d-neighbour there".
+// Wave-uniform l-mer reads, exit once every live candidate of the wave has
+// one. Adds L per live candidate to hc (canonical test count).
+__device__ __forceinline__ void scan_string(const PairJob &J, int i,
+                                            const uint32_t *ch,
+                                            const uint32_t *cl, bool *live,
+                                            unsigned long long &hc)
+{
+    const c_u64 *row = (const c_u64 *)(const void *)(
+        J.planes + (size_t)i * J.L);
+    bool hit[kPairPer];
+#pragma unroll
+    for (int u = 0; u < kPairPer; u++) {
+        hit[u] = !live[u];
+        hc += live[u] ? (unsigned long long)J.L : 0ull;
+    }
+    for (int y0 = 0; y0 < J.L; y0 += 8) {
+        const int y1 = min(y0 + 8, J.L);
+        for (int yy = y0; yy < y1; yy++) {
+            const unsigned long long v = row[yy];
+            const uint32_t vh = (uint32_t)v, vl = (uint32_t)(v >> 32);
+#pragma unroll
+            for (int u = 0; u < kPairPer; u++)
+                hit[u] |= __popc((ch[u] ^ vh) | (cl[u] ^ vl)) <= J.d;
+        }
+        bool done = true;
+#pragma unroll
+        for (int u = 0; u < kPairPer; u++)
+            done &= hit[u];
+        if (__all(done))
+            break;
+    }
+#pragma unroll
+    for (int u = 0; u < kPairPer; u++)
+        live[u] &= hit[u];
+}
+
+// Append the lanes' kept entries with one atomic per wave (lanes that are
+// not active in the wave do not take part).
+__device__ __forceinline__ unsigned long long
+wave_slot(bool keep, unsigned long long *count, unsigned long long &below)
+{
+    const unsigned long long m = __ballot(keep);
+    if (m == 0)
+        return ~0ull;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader)
+        base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return base;
+}
+
+// Survivors of string i: to the next queue, or (after the last string) as
+// codes to the heap.
+__device__ __forceinline__ void emit(const PairJob &J, int i,
+                                     const uint32_t *ch, const uint32_t *cl,
+                                     const bool *live, uint2 *qout,
+                                     unsigned long long *qcount)
+{
+    const bool last = i >= J.n - 1;
+#pragma unroll
+    for (int u = 0; u < kPairPer; u++) {
+        unsigned long long below = 0;
+        const unsigned long long base =
+            wave_slot(live[u], last ? J.heap_top : qcount, below);
+        if (!live[u] || base == ~0ull)
+            continue;
+        const unsigned long long at = base + below;
+        if (last) {
+            uint64_t code = 0;
+            for (int p = 0; p < J.l; p++)
+                code = (code << 2) | (((ch[u] >> p) & 1u) << 1) |
+                       ((cl[u] >> p) & 1u);
+            if (at < J.heap_cap)
+                J.heap[at] = code;
+        } else if (at < J.qcap) {
+            qout[at] = make_uint2(ch[u], cl[u]);
+        } else {
+            atomicOr(J.overflow, 1u);
+        }
+    }
+}
+
+// Candidates of the items [it0, it1) tested against s_3 (or straight to the
+// heap when n = 2); the next item comes from *J.next, which starts at it0.
 __global__ __launch_bounds__(kTPB) void
-k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
+k_pair_filter(PairJob J, unsigned long long it1, unsigned long long npairs)
 {
     __shared__ unsigned long long s_item, s_pair, s_hc;
+    __shared__ PairTuple s_tup[kPairMaxTuples];
     const int tid = threadIdx.x;
     const uint32_t lmask = (J.l >= 32) ? ~0u : ((1u << J.l) - 1u);
     unsigned long long hc = 0;
     if (tid == 0)
         s_hc = 0;
+    for (int i = tid; i < J.ntup; i += kTPB)
+        s_tup[i] = J.tup[i];
     for (;;) {
         __syncthreads();
         if (tid == 0) {
@@ -74,7 +167,7 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
             s_item = it;
             // the pair whose chunk range holds the item
             unsigned long long lo = 0, hi = npairs - 1;
-            if (it < nitems) {
+            if (it < it1) {
                 while (lo < hi) {
                     const unsigned long long mid = (lo + hi + 1) / 2;
                     if (J.item_pos[mid] <= it)
@@ -87,7 +180,7 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
         }
         __syncthreads();
         const unsigned long long it = s_item;
-        if (it >= nitems)
+        if (it >= it1)
             break;
         const unsigned long long pi = s_pair;
         const uint2 pr = J.pairs[pi];
@@ -111,21 +204,33 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
             int lo = t0, hi = t1 - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) / 2;
-                if (J.tup[mid].first <= r)
+                if (s_tup[mid].first <= r)
                     lo = mid;
                 else
                     hi = mid - 1;
             }
-            const PairTuple T = J.tup[lo];
-            uint64_t q = r - T.first;
-            const uint64_t n3 = J.pow3[T.e];
-            const uint64_t ns = J.binom[(J.l - D) * (kMaxL + 1) + T.e];
-            uint64_t agl = q % n3;
-            q /= n3;
-            uint64_t ags = q % ns;
-            q /= ns;
-            uint64_t oth = q & ((1ull << T.c) - 1ull);
-            uint64_t col = q >> T.c;
+            const PairTuple T = s_tup[lo];
+            const uint64_t q64 = r - T.first;
+            // index = ((colouring * 2^c + others) * C(l-D,e) + agreeing set)
+            //         * 3^e + agreeing letters; every factor is < 2^32
+            uint32_t agl, ags, oth, col;
+            if (q64 < (1ull << 32)) {
+                uint32_t q = (uint32_t)q64;
+                agl = q % T.n3;
+                q /= T.n3;
+                ags = q % T.ns;
+                q /= T.ns;
+                oth = q & ((1u << T.c) - 1u);
+                col = q >> T.c;
+            } else {
+                uint64_t q = q64;
+                agl = (uint32_t)(q % T.n3);
+                q /= T.n3;
+                ags = (uint32_t)(q % T.ns);
+                q /= T.ns;
+                oth = (uint32_t)(q & ((1ull << T.c) - 1ull));
+                col = (uint32_t)(q >> T.c);
+            }
             // colour the differing positions in increasing order
             int ra = T.a, rb = T.b, rc = T.c, rem = D;
             uint32_t m = dm;
@@ -133,15 +238,13 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
                 const int p = __ffs(m) - 1;
                 m &= m - 1;
                 rem--;
-                const uint64_t n0 = ra ? multinom(J.fact, rem, ra - 1, rb, rc)
-                                       : 0;
+                const uint32_t n0 = ra ? multi_at(J.multi, rem, ra - 1, rb) : 0u;
                 if (col < n0) {
                     ra--;                                 // x's letter
                     continue;
                 }
                 col -= n0;
-                const uint64_t n1 = rb ? multinom(J.fact, rem, ra, rb - 1, rc)
-                                       : 0;
+                const uint32_t n1 = rb ? multi_at(J.multi, rem, ra, rb - 1) : 0u;
                 const uint32_t xv = (((x.x >> p) & 1u) << 1) | ((x.y >> p) & 1u);
                 const uint32_t yv = (((y.x >> p) & 1u) << 1) | ((y.y >> p) & 1u);
                 if (col < n1) {
@@ -152,8 +255,8 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
                 col -= n1;
                 rc--;                                     // one of the others
                 const uint32_t z = xv ^ yv;
-                const uint32_t w = (oth & 1ull) ? (z == 3u ? 2u : 3u)
-                                                 : (z == 1u ? 2u : 1u);
+                const uint32_t w = (oth & 1u) ? (z == 3u ? 2u : 3u)
+                                              : (z == 1u ? 2u : 1u);
                 oth >>= 1;
                 set_letter(ch[u], cl[u], p, xv ^ w);
             }
@@ -164,71 +267,74 @@ k_pair_filter(PairJob J, unsigned long long nitems, unsigned long long npairs)
                 const int p = __ffs(am) - 1;
                 am &= am - 1;
                 after--;
-                const uint64_t skip = J.binom[after * (kMaxL + 1) + re];
+                const uint32_t skip =
+                    (uint32_t)J.binom[after * (kMaxL + 1) + re];
                 if (ags < skip)
                     continue;
                 ags -= skip;
                 re--;
                 const uint32_t xv = (((x.x >> p) & 1u) << 1) | ((x.y >> p) & 1u);
-                const uint32_t w = 1u + (uint32_t)(agl % 3ull);
-                agl /= 3ull;
+                const uint32_t w = 1u + agl % 3u;
+                agl /= 3u;
                 set_letter(ch[u], cl[u], p, xv ^ w);
             }
         }
-        // strings s_3..s_n in order, early exit per string and per wave
-        for (int i = 2; i < J.n; i++) {
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < kPairPer; u++)
-                any |= live[u];
-            if (__ballot(any) == 0)
-                break;
-            const c_u64 *row = (const c_u64 *)(const void *)(
-                J.planes + (size_t)i * J.L);
-            bool hit[kPairPer];
-#pragma unroll
-            for (int u = 0; u < kPairPer; u++) {
-                hit[u] = !live[u];
-                hc += live[u] ? (unsigned long long)J.L : 0ull;
-            }
-            for (int y0 = 0; y0 < J.L; y0 += 8) {
-                const int y1 = min(y0 + 8, J.L);
-                for (int yy = y0; yy < y1; yy++) {
-                    const unsigned long long v = row[yy];
-                    const uint32_t vh = (uint32_t)v, vl = (uint32_t)(v >> 32);
-#pragma unroll
-                    for (int u = 0; u < kPairPer; u++)
-                        hit[u] |= __popc((ch[u] ^ vh) | (cl[u] ^ vl)) <= J.d;
-                }
-                bool done = true;
-#pragma unroll
-                for (int u = 0; u < kPairPer; u++)
-                    done &= hit[u];
-                if (__all(done))
-                    break;
-            }
-#pragma unroll
-            for (int u = 0; u < kPairPer; u++)
-                live[u] &= hit[u];
-        }
-#pragma unroll
-        for (int u = 0; u < kPairPer; u++) {
-            if (!live[u])
-                continue;
-            uint64_t code = 0;
-            for (int p = 0; p < J.l; p++)
-                code = (code << 2) | (((ch[u] >> p) & 1u) << 1) |
-                       ((cl[u] >> p) & 1u);
-            const unsigned long long at = atomicAdd(J.heap_top, 1ull);
-            if (at < J.heap_cap)
-                J.heap[at] = code;
-        }
+        // s_3 here; the later strings run on the compacted queue
+        if (J.n > 2)
+            scan_string(J, 2, ch, cl, live, hc);
+        emit(J, J.n > 2 ? 2 : 1, ch, cl, live, J.q[0], J.qcount);
     }
     if (hc)
         atomicAdd(&s_hc, hc);
     __syncthreads();
     if (tid == 0 && s_hc)
         atomicAdd(J.tests, s_hc);
+}
+
+// Queue stage: the candidates that passed strings up to i-1 (qin, count in
+// *qin_count) against string i; survivors to qout (or the heap after the
+// last string).
+__global__ __launch_bounds__(kTPB) void
+k_pair_queue(PairJob J, int i, const uint2 *qin,
+             const unsigned long long *qin_count, uint2 *qout,
+             unsigned long long *qout_count)
+{
+    __shared__ unsigned long long s_hc;
+    const int tid = threadIdx.x;
+    unsigned long long hc = 0;
+    if (tid == 0)
+        s_hc = 0;
+    const unsigned long long cnt = min(*qin_count, J.qcap);
+    for (unsigned long long b0 = (unsigned long long)blockIdx.x * kPairChunk;
+         b0 < cnt; b0 += (unsigned long long)gridDim.x * kPairChunk) {
+        uint32_t ch[kPairPer], cl[kPairPer];
+        bool live[kPairPer];
+#pragma unroll
+        for (int u = 0; u < kPairPer; u++) {
+            const unsigned long long k = b0 + (unsigned long long)u * kTPB + tid;
+            live[u] = k < cnt;
+            const uint2 v = live[u] ? qin[k] : make_uint2(0u, 0u);
+            ch[u] = v.x;
+            cl[u] = v.y;
+        }
+        scan_string(J, i, ch, cl, live, hc);
+        emit(J, i, ch, cl, live, qout, qout_count);
+    }
+    if (hc)
+        atomicAdd(&s_hc, hc);
+    __syncthreads();
+    if (tid == 0 && s_hc)
+        atomicAdd(J.tests, s_hc);
+}
+
+hipError_t launch_pair_queue(const PairJob &J, int i, const uint2 *qin,
+                             const unsigned long long *qin_count, uint2 *qout,
+                             unsigned long long *qout_count, int grid,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_queue, dim3(grid), dim3(kTPB), 0, st, J, i, qin,
+                       qin_count, qout, qout_count);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_list(const PairJob &J, hipStream_t st)
@@ -239,14 +345,14 @@ hipError_t launch_pair_list(const PairJob &J, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_pair_filter(const PairJob &J, unsigned long long nitems,
+hipError_t launch_pair_filter(const PairJob &J, unsigned long long it1,
                               unsigned long long npairs, int grid,
                               hipStream_t st)
 {
-    if (nitems == 0 || npairs == 0)
+    if (npairs == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_pair_filter, dim3(grid), dim3(kTPB), 0, st, J,
-                       nitems, npairs);
+    hipLaunchKernelGGL(k_pair_filter, dim3(grid), dim3(kTPB), 0, st, J, it1,
+                       npairs);
     return hipGetLastError();
 }
 

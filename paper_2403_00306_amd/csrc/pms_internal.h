@@ -167,14 +167,22 @@ int alpha_blocks_per_cu();
 struct PairTuple {
     uint64_t first;              // first flat index of this tuple for its D
     uint8_t a, b, c, e;          // letters from x / from y / other on the
-    uint32_t pad;                //   differing positions; changed agreeing
+                                 //   differing positions; changed agreeing
+    uint32_t n3;                 // 3^e
+    uint32_t ns;                 // C(l-D, e)
+    uint32_t pad;
 };
+constexpr int kPairMaxTuples = 1024;   // held in LDS by the filter
+constexpr int kPairMaxD = 20;          // 2d <= 20: multinomials < 2^32
 struct PairJob {
     const uint2 *planes;         // the instance's l-mer planes (row 0 = s_1)
     const uint64_t *nD;          // |B(x,d) ∩ B(y,d)| by D = d_H(x,y)
     const PairTuple *tup;        // tuples of every D, D's at tup_off[D]
     const int *tup_off;
-    const uint64_t *pow3, *fact, *binom;   // binom[n*(kMaxL+1)+k]
+    const uint64_t *binom;       // binom[n*(kMaxL+1)+k]
+    const uint32_t *multi;       // multinomial (r; a, b, r-a-b) at
+                                 //   [(r*(kPairMaxD+1)+a)*(kPairMaxD+1)+b]
+    int ntup;
     uint2 *pairs;                // compatible pairs (index in s_1, in s_2)
     uint32_t *chunks;            // work items per pair
     unsigned long long *npairs, *ncand, *next, *tests;
@@ -183,12 +191,22 @@ struct PairJob {
     uint64_t *heap;              // survivors (unordered, repeats possible)
     unsigned long long *heap_top;
     unsigned long long heap_cap;
+    uint2 *q[2];                 // candidate queues between strings
+    unsigned long long *qcount;  // entries appended to q[0] by the filter
+    unsigned long long qcap;
+    unsigned int *overflow;      // set if a queue overflowed
     int n, L, l, d;
 };
 hipError_t launch_pair_list(const PairJob &J, hipStream_t st);
-hipError_t launch_pair_filter(const PairJob &J, unsigned long long nitems,
+// Candidates of the work items [*J.next, it1) against s_3, survivors to
+// q[0] (count in *J.qcount); then each later string with launch_pair_queue.
+hipError_t launch_pair_filter(const PairJob &J, unsigned long long it1,
                               unsigned long long npairs, int grid,
                               hipStream_t st);
+hipError_t launch_pair_queue(const PairJob &J, int i, const uint2 *qin,
+                             const unsigned long long *qin_count, uint2 *qout,
+                             unsigned long long *qout_count, int grid,
+                             hipStream_t st);
 int pair_chunk();
 int pair_blocks_per_cu();
 

@@ -64,6 +64,8 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
                     t.b = (uint8_t)b;
                     t.c = (uint8_t)cc;
                     t.e = (uint8_t)e;
+                    t.n3 = (uint32_t)pow3[e];
+                    t.ns = (uint32_t)binom[(l - D) * (kMaxL + 1) + e];
                     tup.push_back(t);
                     // work items per pair are 32-bit counts of 1024
                     if (cnt > ((unsigned __int128)1 << 40) ||
@@ -77,6 +79,18 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     }
     for (int D = std::min(2 * d, l) + 1; D <= 2 * d + 2; D++)
         tup_off[D] = (int)tup.size();
+    if (tup.size() > (size_t)kPairMaxTuples)
+        return c->fail(PMS_EINVAL, "pair path: %zu intersection shapes of "
+                       "(%d,%d) above %d", tup.size(), l, d, kPairMaxTuples);
+    // multinomials (r; a, b, r-a-b) for r <= 2d <= 20: at most 3^20 < 2^32
+    const int MD = kPairMaxD + 1;
+    std::vector<uint32_t> multi((size_t)MD * MD * MD, 0);
+    for (int r = 0; r <= kPairMaxD; r++)
+        for (int a = 0; a <= r; a++)
+            for (int b2 = 0; a + b2 <= r; b2++)
+                multi[((size_t)r * MD + a) * MD + b2] =
+                    (uint32_t)(fact[r] / (fact[a] * fact[b2] *
+                                          fact[r - a - b2]));
 
     // device layout (the aux buffer): tables, counters, pair arrays
     size_t off = 0;
@@ -89,10 +103,9 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     const size_t o_tup = take(std::max<size_t>(tup.size(), 1) *
                               sizeof(PairTuple));
     const size_t o_toff = take(tup_off.size() * 4);
-    const size_t o_p3 = take(pow3.size() * 8);
-    const size_t o_fact = take(fact.size() * 8);
+    const size_t o_multi = take(multi.size() * 4);
     const size_t o_bin = take(binom.size() * 8);
-    const size_t o_cnt = take(4 * 8);
+    const size_t o_cnt = take(8 * 8);
     const size_t o_pairs = take(LL * 8);
     const size_t o_chunks = take(LL * 4);
     const size_t o_pos = take((LL + 1) * 8);
@@ -109,29 +122,31 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
                                  hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(b + o_toff, tup_off.data(), tup_off.size() * 4,
                              hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(b + o_p3, pow3.data(), pow3.size() * 8,
-                             hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(b + o_fact, fact.data(), fact.size() * 8,
+    HIPCHK(c, hipMemcpyAsync(b + o_multi, multi.data(), multi.size() * 4,
                              hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(b + o_bin, binom.data(), binom.size() * 8,
                              hipMemcpyHostToDevice, st));
     unsigned long long *cnt = (unsigned long long *)(b + o_cnt);
-    HIPCHK(c, launch_fill_u64(cnt, 4, 0, st));
+    HIPCHK(c, launch_fill_u64(cnt, 8, 0, st));
 
     PairJob J;
     J.planes = I.planes;
     J.nD = (const uint64_t *)(b + o_nD);
     J.tup = (const PairTuple *)(b + o_tup);
     J.tup_off = (const int *)(b + o_toff);
-    J.pow3 = (const uint64_t *)(b + o_p3);
-    J.fact = (const uint64_t *)(b + o_fact);
+    J.multi = (const uint32_t *)(b + o_multi);
     J.binom = (const uint64_t *)(b + o_bin);
+    J.ntup = (int)tup.size();
     J.pairs = (uint2 *)(b + o_pairs);
     J.chunks = (uint32_t *)(b + o_chunks);
     J.npairs = cnt;
     J.ncand = cnt + 1;
     J.next = cnt + 2;
     J.tests = cnt + 3;
+    J.qcount = cnt + 4;                 // cnt[4], cnt[5]: the two queues
+    J.overflow = (unsigned int *)(cnt + 6);
+    J.q[0] = J.q[1] = nullptr;
+    J.qcap = 0;
     J.pairs_cap = LL;
     J.item_pos = (const uint64_t *)(b + o_pos);
     J.heap = I.heap;
@@ -155,11 +170,41 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
         HIPCHK(c, hipStreamSynchronize(st));
         nitems = hp[0];
     }
-    HIPCHK(c, launch_pair_filter(J, nitems, npairs,
-                                 std::max(1, c->n_cu * c->pair_bpc), st));
+    // Queues between strings: a batch of work items at a time, sized so
+    // that even if every candidate passed s_3 the queue holds them; the
+    // later strings run on the compacted queue, stage after stage, with no
+    // host wait in between.
+    const unsigned long long qcap = std::max<unsigned long long>(
+        (unsigned long long)pair_chunk(),
+        std::min<unsigned long long>(1ull << 26, ncand + pair_chunk()));
+    if ((rc = c->alloc(c->alive, 2 * qcap * sizeof(uint2))))
+        return rc;
+    J.q[0] = (uint2 *)c->alive.p;
+    J.q[1] = J.q[0] + qcap;
+    J.qcap = qcap;
+    const unsigned long long per_batch = qcap / pair_chunk();
+    const int grid = std::max(1, c->n_cu * c->pair_bpc);
+    for (unsigned long long lo = 0; lo < nitems; lo += per_batch) {
+        const unsigned long long hi = std::min(nitems, lo + per_batch);
+        HIPCHK(c, launch_fill_u64(J.next, 1, lo, st));
+        HIPCHK(c, launch_fill_u64(J.qcount, 1, 0, st));
+        HIPCHK(c, launch_pair_filter(J, hi, npairs, grid, st));
+        int in = 0;
+        for (int i = 3; i < n; i++) {
+            const int out = in ^ 1;
+            HIPCHK(c, launch_fill_u64(J.qcount + out, 1, 0, st));
+            HIPCHK(c, launch_pair_queue(J, i, J.q[in], J.qcount + in,
+                                        J.q[out], J.qcount + out, grid, st));
+            in = out;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(hp + 2, J.overflow, 4, hipMemcpyDeviceToHost,
+                             st));
     HIPCHK(c, hipMemcpyAsync(hp, I.heap_top, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(hp + 1, J.tests, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    if ((uint32_t)hp[2] != 0)
+        return c->fail(PMS_EDEVICE, "pair path: candidate queue overflow");
     *found = hp[0];
     S.pairs = npairs;
     S.candidates = ncand;

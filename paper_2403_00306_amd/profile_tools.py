@@ -31,6 +31,7 @@ ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.hip",
                   "k_tiled_quorum": "csrc/k_tiles.hip",
                   "k_alpha_filter": "csrc/k_alpha.hip",
+                  "k_pair_filter": "csrc/k_pair.hip",
                   "k_filter": "csrc/k_filter.hip"}
 
 
