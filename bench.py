@@ -352,9 +352,9 @@ def main():
                          "calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not "
-              "supported (multi-GPU sharding is described in DESIGN.md only)"
-              % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU per process; --gpus %d "
+              "is not supported (sharding across GPUs is a design, not "
+              "code)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
