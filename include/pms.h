@@ -17,10 +17,16 @@
  * uppercase 'A','C','G','T'; anything else is PMS_EBASE, and
  * pms_last_error() names the string and offset of the first bad byte.
  *
+ * Variants. pms_solve_quorum returns the (l,d,q)-motifs for any quorum
+ * 1 <= q <= n (Definition 5); pms_solve_alphabet solves the same problem
+ * over another alphabet of 2..32 letters (codes in base sigma, see there);
+ * PMS_PATH_PAIR (an option of the context) computes the plain set from
+ * pairs of l-mers of s_1 and s_2 (Observation 3.3).
+ *
  * Ownership. Inputs are copied before a call returns (pms_submit included),
  * so the caller may free them at once. Result arrays belong to the context
  * and stay valid until the next call on that context that returns results
- * (pms_solve / pms_solve_batch) or until pms_release / pms_destroy.
+ * (pms_solve*, pms_solve_batch) or until pms_release / pms_destroy.
  *
  * Threads. A context is not thread-safe: use one per host thread. The
  * serving entry points (pms_submit / pms_poll / pms_release) may be called
