@@ -45,6 +45,8 @@ struct __align__(16) TileShared {
     unsigned long long red64[kWaves];
     unsigned int red32[kWaves];
     unsigned long long bcast;
+    uint32_t mass[kOrderMax];          // per-tile string order: sphere mass
+    int torder[kOrderMax];             //   of each string, strings by mass
 };
 
 // the filter stage keeps two plane buffers, a code buffer and a chunk of
@@ -406,12 +408,49 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
     __syncthreads();   // the previous tile may still be reading sh.U
 
+    // Strings in ascending order of the word marks their reaching l-mers
+    // would make on this tile (the sizes of their word-level spheres): small
+    // unions empty the intersection soonest and cost least. Any order gives
+    // the same set. One wave per string, sums in registers. The host turns
+    // it on where a pass's marks outweigh the n*L prefix tests it costs.
+    const bool tile_order = I.tile_order != 0 && I.n <= kOrderMax;
+    if (tile_order) {
+        const int wid = tid >> 6, lane = tid & 63;
+        const int *boff = tb.ball_off + q * 8;
+        for (int i = wid; i < I.n; i += kWaves) {
+            const PlaneRow yp = planes_row(I.planes, (size_t)i * I.L);
+            uint32_t mass = 0;
+            for (int j = lane; j < I.L; j += 64) {
+                const uint2 y = yp[j];
+                const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
+                if (k <= I.d)
+                    mass += (uint32_t)boff[min(I.d - k, q) + 1];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                mass += __shfl_xor(mass, o, 64);
+            if (lane == 0)
+                sh.mass[i] = mass;
+        }
+        __syncthreads();
+        if (tid < I.n) {
+            const uint32_t mi = sh.mass[tid];
+            int rank = 0;
+            for (int j = 0; j < I.n; j++) {
+                const uint32_t mj = sh.mass[j];
+                rank += (mj < mi) || (mj == mi && j < tid);
+            }
+            sh.torder[rank] = tid;
+        }
+        __syncthreads();
+    }
+
     unsigned long long A[kWordsPerThread];
     unsigned long long total = 0;
     int si = 0;
     bool to_filter = false;
     for (si = 0; si < I.n; si++) {
-        const int seq = uni(I.order[si]);
+        const int seq = tile_order ? uni(sh.torder[si]) : uni(I.order[si]);
         // U is all zero here: cleared at kernel start, by the previous
         // pass's AND step, or after the previous tile's emission
         const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
@@ -518,7 +557,9 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         const uint2 *plc = cur ? plb1 : plb0;
         const uint64_t *cdc = cur ? cdb1 : sh.surv;
         const uint2 *yrow = reinterpret_cast<const uint2 *>(I.planes) +
-                            (size_t)uni(I.order[sj]) * (size_t)L;
+                            (size_t)(tile_order ? uni(sh.torder[sj])
+                                                : uni(I.order[sj])) *
+                                (size_t)L;
         const uint2 cp = (ci < N) ? plc[ci] : make_uint2(0, 0);
         uint32_t mind = 255;
         bool found = false;                 // my group has a hit

@@ -17,6 +17,7 @@ constexpr int kWordsPerThread = kMaxWords / kTPB;   // 16
 constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
 constexpr int kDefaultSurv = 64;   // default threshold to enter it
+constexpr int kOrderMax = 64;      // per-tile string order for n up to this
 constexpr int kQuorumMaxSuffix = 8;   // quorum tiles: 4^8 codes, so that
 constexpr int kQuorumMaxMiss = 30;    //   5-bit miss counters of every code
                                       //   stay in registers (4 words/thread)
@@ -86,7 +87,7 @@ struct InstDev {
     int n, m, l, d, L, s, surv_t, wpr;
     int q;                   // quorum: a motif needs d-neighbours in at
                              //   least q strings (q = n: every string)
-    int pad_q;
+    int tile_order;          // tiled path: order the strings per tile
 };
 
 // A contiguous range of one instance's tiles.
