@@ -47,12 +47,15 @@ struct __align__(16) TileShared {
     unsigned long long bcast;
     uint32_t mass[kOrderMax];          // per-tile string order: sphere mass
     int torder[kOrderMax];             //   of each string, strings by mass
+    uint32_t cw[kMaxL + 1];            //   word entries of B at radius r
 };
 
-// the filter stage keeps two plane buffers, a code buffer and a chunk of
-// the current string's l-mer planes in sh.U
-constexpr int kFiltChunk = kMaxWords - 3 * kSurvMax;
-static_assert(kFiltChunk >= kTPB, "filter scratch exceeds the tile");
+// the filter stage keeps two plane buffers, a code buffer and the hit
+// flags in sh.U; each lane holds kFiltPer l-mers of a string at a time
+constexpr int kFiltPer = 3;
+constexpr int kFiltWords = 3 * kSurvMax + kSurvMax / 2;
+static_assert(kFiltWords <= kMaxWords && kSurvMax <= kTPB,
+              "filter scratch exceeds the tile");
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 {
@@ -406,25 +409,35 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     uint32_t Phi, Plo;
     prefix_planes(t, pl, Phi, Plo);
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
-    __syncthreads();   // the previous tile may still be reading sh.U
-
     // Strings in ascending order of the word marks their reaching l-mers
     // would make on this tile (the sizes of their word-level spheres): small
     // unions empty the intersection soonest and cost least. Any order gives
-    // the same set. One wave per string, sums in registers. The host turns
-    // it on where a pass's marks outweigh the n*L prefix tests it costs.
+    // the same set. The host turns it on where a pass's marks outweigh the
+    // n*L prefix tests it costs.
     const bool tile_order = I.tile_order != 0 && I.n <= kOrderMax;
+    if (tile_order && tid <= I.d)
+        sh.cw[tid] = (uint32_t)tb.ball_off[q * 8 + min(tid, q) + 1];
+    __syncthreads();   // the previous tile may still be reading sh.U
     if (tile_order) {
+        // one wave per string; each lane loads kOrdPer l-mers at once so
+        // that a string costs about one round trip to L2
+        constexpr int kOrdPer = 8;
         const int wid = tid >> 6, lane = tid & 63;
-        const int *boff = tb.ball_off + q * 8;
         for (int i = wid; i < I.n; i += kWaves) {
             const PlaneRow yp = planes_row(I.planes, (size_t)i * I.L);
             uint32_t mass = 0;
-            for (int j = lane; j < I.L; j += 64) {
-                const uint2 y = yp[j];
-                const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
-                if (k <= I.d)
-                    mass += (uint32_t)boff[min(I.d - k, q) + 1];
+            for (int j0 = lane; j0 < I.L; j0 += 64 * kOrdPer) {
+                uint2 y[kOrdPer];
+#pragma unroll
+                for (int u = 0; u < kOrdPer; u++)
+                    y[u] = yp[min(j0 + 64 * u, I.L - 1)];
+#pragma unroll
+                for (int u = 0; u < kOrdPer; u++) {
+                    const int k = __popc(((y[u].x ^ Phi) | (y[u].y ^ Plo)) &
+                                         premask);
+                    if (j0 + 64 * u < I.L && k <= I.d)
+                        mass += sh.cw[I.d - k];
+                }
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1)
@@ -488,17 +501,16 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         }
         return;
     }
-    // the intersection back to LDS, in word order
-#pragma unroll
-    for (int k = 0; k < kWordsPerThread; k++) {
-        const int w = tid + k * kTPB;
-        if (w < W)
-            sh.U[w] = A[k];
-    }
-    __syncthreads();
-
     if (!to_filter) {
-        // every string ANDed in: all remaining codes are motifs
+        // every string ANDed in: all remaining codes are motifs; the
+        // intersection goes back to LDS, in word order, and out in code order
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; k++) {
+            const int w = tid + k * kTPB;
+            if (w < W)
+                sh.U[w] = A[k];
+        }
+        __syncthreads();
         if (tid == 0) {
             const unsigned long long off = atomicAdd(heap_top, total);
             sh.bcast = off;
@@ -516,95 +528,117 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     }
 
     // ---- filter stage: test the few codes left against the rest --------
-    // The live codes are kept compacted, in code order, with their bit
-    // planes. For each remaining string every code gets G lanes (G = 256/N
-    // rounded down to a power of two, at most one wave) that split the
-    // string's l-mers; a group stops as soon as one of its lanes finds an
-    // l-mer within distance d, and the codes without such an l-mer drop
-    // out before the next string. Codes and planes are double-buffered in
-    // the tile's LDS words, which are free during this stage.
-    emit_words(sh, W, t, s, sh.surv, true, sh.red32);
-    __syncthreads();
-    int N = (int)total;
-    uint2 mypl = make_uint2(0, 0);
-    if (tid < N) {
-        const uint64_t code = sh.surv[tid];
-        sh.U[(code >> 6) & (uint64_t)(W - 1)] = 0;   // the word A left there
-        mypl = code_planes(code, I.l);
-    }
-    __syncthreads();
+    // The live codes (at most surv_t <= kSurvMax) are listed straight from
+    // the registers with their bit planes, into LDS words that are all zero
+    // at this point (U was cleared as it was read). Each lane holds up to
+    // kFiltPer l-mers of the current string in registers, loaded one string
+    // ahead, and every wave tests every live code (read from LDS with one
+    // broadcast per wave) against its l-mers; a code with a hit in any wave
+    // is flagged and the unflagged ones drop out before the next string.
+    // The list is in thread order; the survivors are ranked by code when
+    // they are written out.
     uint2 *const plb0 = reinterpret_cast<uint2 *>(sh.U);
     uint2 *const plb1 = plb0 + kSurvMax;
     uint64_t *const cdb1 = reinterpret_cast<uint64_t *>(sh.U) + 2 * kSurvMax;
-    if (tid < N)
-        plb0[tid] = mypl;
-    __syncthreads();
-    uint2 *const ysh = reinterpret_cast<uint2 *>(sh.U) + 3 * kSurvMax;
-    const int lane = tid & 63;
+    uint32_t *const hitf = reinterpret_cast<uint32_t *>(
+        reinterpret_cast<uint64_t *>(sh.U) + 3 * kSurvMax);
     const int L = I.L;
+    int N;
+    {
+        unsigned int c = 0;
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; k++)
+            if (tid + k * kTPB < W)
+                c += (unsigned int)__popcll(A[k]);
+        unsigned int nt;
+        unsigned int pos = block_exscan(c, sh.red32, &nt);
+        const uint64_t base = t << (2 * s);
+#pragma unroll
+        for (int k = 0; k < kWordsPerThread; k++) {
+            const int w = tid + k * kTPB;
+            unsigned long long v = (w < W) ? A[k] : 0ull;
+            while (v) {
+                const int b = __ffsll(v) - 1;
+                v &= v - 1;
+                const uint64_t code = base | ((uint64_t)w << 6) | (uint64_t)b;
+                sh.surv[pos] = code;
+                plb0[pos] = code_planes(code, I.l);
+                pos++;
+            }
+        }
+        N = (int)nt;
+    }
+    auto seq_at = [&](int j) {
+        return tile_order ? uni(sh.torder[j]) : uni(I.order[j]);
+    };
+    // l-mers r0 + tid + u*kTPB of string `sq`; past the end, the last l-mer
+    // again (a repeat leaves every minimum unchanged)
+    auto load_ys = [&](int sq, int r0, uint2 (&y)[kFiltPer]) {
+        const uint2 *row = I.planes + (size_t)sq * (size_t)L;
+#pragma unroll
+        for (int u = 0; u < kFiltPer; u++)
+            y[u] = row[min(r0 + tid + u * kTPB, L - 1)];
+    };
+    constexpr int kRound = kFiltPer * kTPB;
+    const int rounds = (L + kRound - 1) / kRound;
+    const int lane = tid & 63;
+    uint2 y[kFiltPer];
+    if (si + 1 < I.n)
+        load_ys(seq_at(si + 1), 0, y);
+    __syncthreads();   // the list is complete
     int cur = 0;
     for (int sj = si + 1; sj < I.n && N > 0; sj++) {
         if (tid == 0)
             acc.ftests += (unsigned long long)N * (unsigned long long)L;
-        int lg = 6;
-        while (lg > 0 && (N << lg) > kTPB)
-            lg--;
-        const int G = 1 << lg;
-        const int ci = tid >> lg, sub = tid & (G - 1);
-        const unsigned long long gmask =
-            (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-        const int gbase = lane & ~(G - 1);
         const uint2 *plc = cur ? plb1 : plb0;
         const uint64_t *cdc = cur ? cdb1 : sh.surv;
-        const uint2 *yrow = reinterpret_cast<const uint2 *>(I.planes) +
-                            (size_t)(tile_order ? uni(sh.torder[sj])
-                                                : uni(I.order[sj])) *
-                                (size_t)L;
-        const uint2 cp = (ci < N) ? plc[ci] : make_uint2(0, 0);
-        uint32_t mind = 255;
-        bool found = false;                 // my group has a hit
-        for (int c0 = 0; c0 < L; c0 += kFiltChunk) {
-            // the string's planes, one chunk at a time, into LDS
-            const int len = min(kFiltChunk, L - c0);
-            for (int j = tid; j < len; j += kTPB)
-                ysh[j] = yrow[c0 + j];
-            __syncthreads();
-            if (ci < N && !found) {
-                // indexes past the end repeat the chunk's last l-mer
-                for (int j = sub;;) {
+        for (int r = 0; r < rounds; r++) {
+            // the next load: this string's next round, else the next
+            // string's first
+            uint2 yn[kFiltPer];
+            if (r + 1 < rounds)
+                load_ys(seq_at(sj), (r + 1) * kRound, yn);
+            else if (sj + 1 < I.n)
+                load_ys(seq_at(sj + 1), 0, yn);
+            for (int c0 = 0; c0 < N; c0 += 4) {
+                uint2 cp[4];
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    cp[v] = plc[min(c0 + v, N - 1)];
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
                     uint32_t h = 255;
 #pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const uint2 y = ysh[min(j + u * G, len - 1)];
-                        h = min(h, (uint32_t)__popc((cp.x ^ y.x) | (cp.y ^ y.y)));
-                    }
-                    mind = min(mind, h);
-                    j += 8 * G;
-                    const unsigned long long hb = __ballot(mind <= (uint32_t)I.d);
-                    if (j >= len || ((hb >> gbase) & gmask) != 0)
-                        break;
+                    for (int u = 0; u < kFiltPer; u++)
+                        h = min(h, (uint32_t)__popc((cp[v].x ^ y[u].x) |
+                                                    (cp[v].y ^ y[u].y)));
+                    const unsigned long long b =
+                        __ballot(h <= (uint32_t)I.d);
+                    if (b != 0 && lane == 0)
+                        hitf[min(c0 + v, N - 1)] = 1u;
                 }
             }
-            found = ((__ballot(mind <= (uint32_t)I.d) >> gbase) & gmask) != 0;
-            // (a barrier either way: the next chunk or string rewrites ysh)
-            if (c0 + kFiltChunk >= L)
-                __syncthreads();
-            else if (__syncthreads_count(ci < N && !found) == 0)
-                break;
+#pragma unroll
+            for (int u = 0; u < kFiltPer; u++)
+                y[u] = yn[u];
         }
-        const unsigned long long hb = __ballot(mind <= (uint32_t)I.d);
-        const bool keep = sub == 0 && ci < N && ((hb >> gbase) & gmask) != 0;
+        __syncthreads();   // every wave's flags are in
+        bool keep = false;
+        if (tid < N) {
+            keep = hitf[tid] != 0u;
+            hitf[tid] = 0u;
+        }
         unsigned int nkeep;
         const unsigned int pos = block_exscan(keep ? 1u : 0u, sh.red32, &nkeep);
         if (keep) {
-            (cur ? plb0 : plb1)[pos] = plc[ci];
-            (cur ? sh.surv : cdb1)[pos] = cdc[ci];
+            (cur ? plb0 : plb1)[pos] = plc[tid];
+            (cur ? sh.surv : cdb1)[pos] = cdc[tid];
         }
         __syncthreads();
         cur ^= 1;
         N = (int)nkeep;
     }
-    // the survivors, in code order, into the heap
+    // the survivors into the heap, each at its rank among them by code
     const uint64_t *cdc = cur ? cdb1 : sh.surv;
     if (tid == 0) {
         unsigned long long off = 0;
@@ -616,12 +650,16 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     }
     __syncthreads();
     const unsigned long long off = sh.bcast;
-    if (tid < N && off + (unsigned long long)N <= heap_cap)
-        heap[off + tid] = cdc[tid];
+    if (tid < N && off + (unsigned long long)N <= heap_cap) {
+        const uint64_t me = cdc[tid];
+        int rank = 0;
+        for (int j = 0; j < N; j++)
+            rank += cdc[j] < me ? 1 : 0;
+        heap[off + rank] = me;
+    }
     __syncthreads();
     // clear the scratch words for the next tile
-    const int used = 3 * kSurvMax + min(L, kFiltChunk);
-    for (int w = tid; w < used; w += kTPB)
+    for (int w = tid; w < kFiltWords; w += kTPB)
         sh.U[w] = 0;
 }
 

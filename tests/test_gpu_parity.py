@@ -229,6 +229,20 @@ def test_tile_shapes_do_not_change_result():
                 assert c.stats()["tile_suffix"] == s
 
 
+def test_tile_order_and_long_strings():
+    # s = 9 turns the per-tile string order on (a pass's word marks well
+    # above the n*L prefix tests) and L = 990 takes the survivor stage over
+    # two register rounds per string; t = 1 and 256 bound its list size
+    inst = pmsgen.planted(9, 16, 1000, 11, 3)
+    want = oracle_set(inst.seqs, inst.n, inst.m, 11, 3)
+    with pms.Context(path=pms.PATH_TILED) as c:
+        for t in (1, 64, 256):
+            c.set_tile_config(11, 3, 9, t)
+            say("order/long t", t)
+            got = c.solve(inst.seqs, inst.n, inst.m, 11, 3)
+            np.testing.assert_array_equal(got, want, err_msg="t=%d" % t)
+
+
 def test_repeat_runs_identical(ctx):
     inst = pmsgen.plain("pms_13_4", 4)
     a = ctx.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d)
