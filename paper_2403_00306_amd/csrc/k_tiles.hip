@@ -395,7 +395,7 @@ struct StatAcc {
 
 // One tile of the tiled path.
 __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
-                         const Tables &tb, StatAcc &acc)
+                         const Tables &tb, StatAcc &acc, int order_mode)
 {
     uint32_t *tile_cnt = I.tile_cnt;
     uint64_t *tile_heap_off = I.tile_heap_off;
@@ -413,12 +413,25 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     // would make on this tile (the sizes of their word-level spheres): small
     // unions empty the intersection soonest and cost least. Any order gives
     // the same set. The host turns it on where a pass's marks outweigh the
-    // n*L prefix tests it costs.
+    // n*L prefix tests it costs. order_mode: 0 keeps the previous tile's
+    // order, 1 orders for this tile alone, 2 for the kOrderReuse sibling
+    // tiles that share the prefix without its last e = log4(kOrderReuse)
+    // bases (the sum of their masses: an l-mer at distance k from that
+    // shorter prefix is at k + j from C(e,j) 3^j of the siblings).
     const bool tile_order = I.tile_order != 0 && I.n <= kOrderMax;
-    if (tile_order && tid <= I.d)
-        sh.cw[tid] = (uint32_t)tb.ball_off[q * 8 + min(tid, q) + 1];
+    const bool make_order = tile_order && order_mode != 0;
+    const int oe = (order_mode == 2) ? min(kOrderReuseLog4, pl) : 0;
+    const uint32_t omask = premask & ~(((1u << oe) - 1u) << (pl - oe));
+    if (make_order && tid <= I.d) {
+        uint32_t v = 0, cf = 1;
+        for (int j = 0; j <= oe && tid + j <= I.d; j++) {
+            v += cf * (uint32_t)tb.ball_off[q * 8 + min(I.d - tid - j, q) + 1];
+            cf = cf * 3u * (uint32_t)(oe - j) / (uint32_t)(j + 1);
+        }
+        sh.cw[tid] = v;   // indexed by k, not by the radius d - k
+    }
     __syncthreads();   // the previous tile may still be reading sh.U
-    if (tile_order) {
+    if (make_order) {
         // one wave per string; each lane loads kOrdPer l-mers at once so
         // that a string costs about one round trip to L2
         constexpr int kOrdPer = 8;
@@ -434,9 +447,9 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
 #pragma unroll
                 for (int u = 0; u < kOrdPer; u++) {
                     const int k = __popc(((y[u].x ^ Phi) | (y[u].y ^ Plo)) &
-                                         premask);
+                                         omask);
                     if (j0 + 64 * u < I.L && k <= I.d)
-                        mass += sh.cw[I.d - k];
+                        mass += sh.cw[k];
                 }
             }
 #pragma unroll
@@ -812,7 +825,10 @@ __device__ __forceinline__ void drain_items(const InstDev *insts,
             if (Quorum)
                 run_tile_quorum(I, t, sh, tb, acc);
             else
-                run_tile(I, t, sh, tb, acc);
+                run_tile(I, t, sh, tb, acc,
+                         (t != w.t0 && (t & (uint64_t)(kOrderReuse - 1)) != 0)
+                             ? 0
+                             : (w.t1 - w.t0 >= 2 ? 2 : 1));
         }
     }
     if (threadIdx.x == 0 && stats) {

@@ -580,7 +580,13 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             res->count = total;
         } else if (P.path == PMS_PATH_TILED) {
             const uint64_t max_items = 1u << 20;
-            const uint64_t chunk = (ntiles + max_items - 1) / max_items;
+            uint64_t chunk = (ntiles + max_items - 1) / max_items;
+            // sibling tiles share one string order: items of kOrderReuse
+            // tiles where that still leaves every workgroup many items
+            const uint64_t grid_tiles =
+                (uint64_t)grid_for(c, c->tiled_bpc) * kOrderReuse * 4;
+            if (!quorum && I.tile_order && ntiles >= grid_tiles)
+                chunk = std::max<uint64_t>(chunk, kOrderReuse);
             const uint64_t nitems = (ntiles + chunk - 1) / chunk;
             if (quorum)
                 HIPCHK(c, launch_tiled_quorum(d_inst, nullptr, (int)nitems,

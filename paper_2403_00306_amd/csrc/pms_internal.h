@@ -18,6 +18,11 @@ constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
 constexpr int kDefaultSurv = 64;   // default threshold to enter it
 constexpr int kOrderMax = 64;      // per-tile string order for n up to this
+#ifndef PMS_ORDER_REUSE
+#define PMS_ORDER_REUSE 4
+#endif
+constexpr int kOrderReuse = PMS_ORDER_REUSE;   // tiles sharing one order
+constexpr int kOrderReuseLog4 = kOrderReuse >= 16 ? 2 : kOrderReuse >= 4 ? 1 : 0;
 constexpr int kQuorumMaxSuffix = 8;   // quorum tiles: 4^8 codes, so that
 constexpr int kQuorumMaxMiss = 30;    //   5-bit miss counters of every code
                                       //   stay in registers (4 words/thread)
