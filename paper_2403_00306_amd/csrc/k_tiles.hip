@@ -411,8 +411,8 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
     // Strings in ascending order of the word marks their reaching l-mers
     // would make on this tile (the sizes of their word-level spheres): small
-    // unions empty the intersection soonest and cost least. Any order gives
-    // the same set. The host turns it on where a pass's marks outweigh the
+    // unions empty the intersection soonest and cost least, as PMS8's rows
+    // sorted by size do (Sec. 3.2.4). Any order gives the same set. The host turns it on where a pass's marks outweigh the
     // n*L prefix tests it costs. order_mode: 0 keeps the previous tile's
     // order, 1 orders for this tile alone, 2 for the kOrderReuse sibling
     // tiles that share the prefix without its last e = log4(kOrderReuse)

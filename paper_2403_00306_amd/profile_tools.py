@@ -25,6 +25,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -35,9 +36,22 @@ KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.
                   "k_filter": "csrc/k_filter.hip"}
 
 
+def _code_text(path: str) -> str:
+    """The file without comments and with whitespace collapsed, so that a
+    comment edit does not mark a profile as stale."""
+    src = open(path, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def source_hash(kernel: str) -> str:
-    path = os.path.join(HERE, KERNEL_SOURCES[kernel])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel's source file and the shared device header (the
+    constants that shape every kernel), code only."""
+    h = hashlib.sha256()
+    for rel in (KERNEL_SOURCES[kernel], "csrc/pms_internal.h"):
+        h.update(_code_text(os.path.join(HERE, rel)).encode())
+    return h.hexdigest()[:16]
 
 
 def short(name: str) -> str:
