@@ -487,8 +487,10 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             const int w = tid + k * kTPB;
             if (w < W) {
                 const uint32_t pw = wpos((uint32_t)w);
-                const unsigned long long u = sh.U[pw];
-                sh.U[pw] = 0;
+                // read and clear in one LDS instruction
+                const unsigned long long u = __hip_atomic_exchange(
+                    &sh.U[pw], 0ull, __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 A[k] = (si == 0) ? u : (A[k] & u);
                 cnt += __popcll(A[k]);
             }
