@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("tile_passes", ctypes.c_uint64), ("marks", ctypes.c_uint64),
                 ("filter_tests", ctypes.c_uint64),
                 ("bytes_main", ctypes.c_uint64), ("retries", ctypes.c_uint64),
-                ("pairs", ctypes.c_uint64), ("candidates", ctypes.c_uint64)]
+                ("pairs", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("tile_threads", ctypes.c_int)]
 
 
 class ServeStats(ctypes.Structure):

@@ -29,6 +29,13 @@
 
 namespace pms {
 
+// The tile code is written for a workgroup of TPB threads: kTPB (256, four
+// waves) for every tiled kernel, and kTPBWide (512, eight waves at up to 64
+// VGPRs) for a second plain-path kernel that keeps twice the waves per CU
+// in flight; the planner takes it for tiles of 4^9 codes. Inside the
+// templates kTPB, kWaves and kWordsPerThread are redeclared for TPB.
+constexpr int kTPBWide = 512;
+constexpr int kMaxTileWaves = kTPBWide / 64;
 constexpr int kYPer = (kYChunk + kTPB - 1) / kTPB;    // l-mers per thread
 constexpr int kYList = kYChunk + 4 * (kMaxL + 1);      // radius classes
                                                        // start 4-aligned
@@ -42,8 +49,8 @@ struct __align__(16) TileShared {
     int rcnt[kMaxL + 1];               // reaching l-mers per radius r
     int roff[kMaxL + 2];
     int rpos[kMaxL + 1];
-    unsigned long long red64[kWaves];
-    unsigned int red32[kWaves];
+    unsigned long long red64[kMaxTileWaves];
+    unsigned int red32[kMaxTileWaves];
     unsigned long long bcast;
     uint32_t mass[kOrderMax];          // per-tile string order: sphere mass
     int torder[kOrderMax];             //   of each string, strings by mass
@@ -66,9 +73,11 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 }
 
 // Sum over the workgroup; every thread gets the total.
+template <int TPB>
 __device__ __forceinline__ unsigned long long
 block_sum64(unsigned long long v, unsigned long long *red)
 {
+    constexpr int kWaves = TPB / 64;
     v = wave_sum64(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
@@ -82,9 +91,11 @@ block_sum64(unsigned long long v, unsigned long long *red)
 }
 
 // Exclusive prefix sum over the workgroup in thread order.
+template <int TPB>
 __device__ __forceinline__ unsigned int
 block_exscan(unsigned int v, unsigned int *red, unsigned int *total)
 {
+    constexpr int kWaves = TPB / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     unsigned int x = v;
 #pragma unroll
@@ -168,11 +179,14 @@ __device__ __forceinline__ void or64_at(TileShared &sh, uint32_t off,
 // more than kTPB/2 entries every wave walks the same l-mers (64 read at
 // once, then broadcast into scalar registers by readlane); a smaller
 // sphere is repeated in 256/bs lane groups that walk different l-mers.
+template <int TPB>
 __device__ unsigned long long mark_string(const InstDev &I, int seq,
                                           uint32_t Phi, uint32_t Plo,
                                           uint32_t premask, TileShared &sh,
                                           const Tables &tb)
 {
+    constexpr int kTPB = TPB;
+    constexpr int kYPer = (kYChunk + TPB - 1) / TPB;
     const int tid = threadIdx.x;
     const int d = I.d, s = I.s, q = s - 3;
     const PlaneRow yp = planes_row(I.planes, (size_t)seq * I.L);
@@ -352,9 +366,11 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
 // Write the set bits of the tile (words in sh.U) as ascending codes to
 // dst[0..). Thread t owns a contiguous block of words so that thread order
 // is code order. Codes: (tile << 2s) | (word << 6) | bit.
+template <int TPB>
 __device__ void emit_words(const TileShared &sh, int W, uint64_t tile, int s,
                            uint64_t *dst, bool write, unsigned int *red)
 {
+    constexpr int kTPB = TPB;
     const int tid = threadIdx.x;
     const int per = (W + kTPB - 1) / kTPB;
     const int w0 = tid * per;
@@ -363,7 +379,7 @@ __device__ void emit_words(const TileShared &sh, int W, uint64_t tile, int s,
     for (int w = w0; w < w1; w++)
         cnt += __popcll(sh.U[w]);
     unsigned int tot;
-    unsigned int pos = block_exscan(cnt, red, &tot);
+    unsigned int pos = block_exscan<TPB>(cnt, red, &tot);
     if (!write)
         return;
     const uint64_t base = tile << (2 * s);
@@ -394,9 +410,14 @@ struct StatAcc {
 };
 
 // One tile of the tiled path.
+template <int TPB>
 __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                          const Tables &tb, StatAcc &acc, int order_mode)
 {
+    constexpr int kTPB = TPB, kWaves = TPB / 64;
+    constexpr int kWordsPerThread = kMaxWords / TPB;
+    // l-mers per lane in the survivor stage (one round covers 768 or 1024)
+    constexpr int kFiltPer = TPB >= kTPBWide ? 2 : 3;
     uint32_t *tile_cnt = I.tile_cnt;
     uint64_t *tile_heap_off = I.tile_heap_off;
     uint64_t *heap = I.heap;
@@ -434,7 +455,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     if (make_order) {
         // one wave per string; each lane loads kOrdPer l-mers at once so
         // that a string costs about one round trip to L2
-        constexpr int kOrdPer = 8;
+        constexpr int kOrdPer = TPB >= kTPBWide ? 4 : 8;
         const int wid = tid >> 6, lane = tid & 63;
         for (int i = wid; i < I.n; i += kWaves) {
             const PlaneRow yp = planes_row(I.planes, (size_t)i * I.L);
@@ -479,7 +500,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         const int seq = tile_order ? uni(sh.torder[si]) : uni(I.order[si]);
         // U is all zero here: cleared at kernel start, by the previous
         // pass's AND step, or after the previous tile's emission
-        const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
+        const unsigned long long mk = mark_string<TPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         unsigned long long cnt = 0;
 #pragma unroll
@@ -495,7 +516,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 cnt += __popcll(A[k]);
             }
         }
-        total = block_sum64(cnt, sh.red64);
+        total = block_sum64<TPB>(cnt, sh.red64);
         if (tid == 0) {
             acc.passes++;
             acc.marks += mk;
@@ -535,7 +556,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         __syncthreads();
         const unsigned long long off = uni(sh.bcast);
         const bool fits = off + total <= heap_cap;
-        emit_words(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
+        emit_words<TPB>(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
         __syncthreads();
         for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
             sh.U[w] = 0;
@@ -566,7 +587,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             if (tid + k * kTPB < W)
                 c += (unsigned int)__popcll(A[k]);
         unsigned int nt;
-        unsigned int pos = block_exscan(c, sh.red32, &nt);
+        unsigned int pos = block_exscan<TPB>(c, sh.red32, &nt);
         const uint64_t base = t << (2 * s);
 #pragma unroll
         for (int k = 0; k < kWordsPerThread; k++) {
@@ -644,7 +665,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             hitf[tid] = 0u;
         }
         unsigned int nkeep;
-        const unsigned int pos = block_exscan(keep ? 1u : 0u, sh.red32, &nkeep);
+        const unsigned int pos = block_exscan<TPB>(keep ? 1u : 0u, sh.red32, &nkeep);
         if (keep) {
             (cur ? plb0 : plb1)[pos] = plc[tid];
             (cur ? sh.surv : cdb1)[pos] = cdc[tid];
@@ -714,7 +735,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
     bool any = true;
     for (int si = 0; si < I.n; si++) {
         const int seq = uni(I.order[si]);
-        const unsigned long long mk = mark_string(I, seq, Phi, Plo, premask,
+        const unsigned long long mk = mark_string<kTPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         int nz = 0;
 #pragma unroll
@@ -774,7 +795,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
             cnt += __popcll(live[k]);
         }
     }
-    const unsigned long long total = block_sum64(cnt, sh.red64);
+    const unsigned long long total = block_sum64<kTPB>(cnt, sh.red64);
     if (tid == 0) {
         const unsigned long long off = atomicAdd(I.heap_top, total);
         sh.bcast = off;
@@ -784,7 +805,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
     __syncthreads();
     const unsigned long long off = uni(sh.bcast);
     const bool fits = off + total <= I.heap_cap;
-    emit_words(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
+    emit_words<kTPB>(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
     __syncthreads();
     for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
         sh.U[w] = 0;
@@ -792,12 +813,13 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
 
 // Persistent loop shared by the tiled kernels: workgroups take work items
 // (tile ranges) from a counter until none is left.
-template <bool Quorum>
+template <int TPB, bool Quorum>
 __device__ __forceinline__ void drain_items(const InstDev *insts,
                                             const WorkItem *items, int nitems,
                                             uint64_t chunk, unsigned int *next,
                                             const Tables &tb, TileStats *stats)
 {
+    constexpr int kTPB = TPB;
     __shared__ TileShared sh;
     __shared__ int s_item;
     for (int i = threadIdx.x; i < 256; i += kTPB)
@@ -827,7 +849,7 @@ __device__ __forceinline__ void drain_items(const InstDev *insts,
             if (Quorum)
                 run_tile_quorum(I, t, sh, tb, acc);
             else
-                run_tile(I, t, sh, tb, acc,
+                run_tile<TPB>(I, t, sh, tb, acc,
                          (t != w.t0 && (t & (uint64_t)(kOrderReuse - 1)) != 0)
                              ? 0
                              : (w.t1 - w.t0 >= 2 ? 2 : 1));
@@ -841,11 +863,20 @@ __device__ __forceinline__ void drain_items(const InstDev *insts,
     }
 }
 
-__global__ __launch_bounds__(kTPB, 4) void
+// (launch bounds: four workgroups per CU, i.e. TPB/64 waves per SIMD)
+__global__ __launch_bounds__(kTPB, kTPB / 64) void
 k_tiled(const InstDev *insts, const WorkItem *items, int nitems,
         uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
 {
-    drain_items<false>(insts, items, nitems, chunk, next, tb, stats);
+    drain_items<kTPB, false>(insts, items, nitems, chunk, next, tb, stats);
+}
+
+__global__ __launch_bounds__(kTPBWide, kTPBWide / 64) void
+k_tiled_512(const InstDev *insts, const WorkItem *items, int nitems,
+            uint64_t chunk, unsigned int *next, Tables tb, TileStats *stats)
+{
+    drain_items<kTPBWide, false>(insts, items, nitems, chunk, next, tb,
+                                 stats);
 }
 
 __global__ __launch_bounds__(kTPB, 4) void
@@ -853,17 +884,22 @@ k_tiled_quorum(const InstDev *insts, const WorkItem *items, int nitems,
                uint64_t chunk, unsigned int *next, Tables tb,
                TileStats *stats)
 {
-    drain_items<true>(insts, items, nitems, chunk, next, tb, stats);
+    drain_items<kTPB, true>(insts, items, nitems, chunk, next, tb, stats);
 }
 
 hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
                         int nitems, uint64_t chunk, unsigned int *d_next,
-                        Tables tb, TileStats *stats, int grid, hipStream_t st)
+                        Tables tb, TileStats *stats, int grid, hipStream_t st,
+                        bool wide)
 {
     if (nitems <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_tiled, dim3(grid), dim3(kTPB), 0, st, d_insts,
-                       d_items, nitems, chunk, d_next, tb, stats);
+    if (wide)
+        hipLaunchKernelGGL(k_tiled_512, dim3(grid), dim3(kTPBWide), 0, st,
+                           d_insts, d_items, nitems, chunk, d_next, tb, stats);
+    else
+        hipLaunchKernelGGL(k_tiled, dim3(grid), dim3(kTPB), 0, st, d_insts,
+                           d_items, nitems, chunk, d_next, tb, stats);
     return hipGetLastError();
 }
 
@@ -889,12 +925,15 @@ int tiled_quorum_blocks_per_cu()
     return nb;
 }
 
-int tiled_blocks_per_cu()
+int tiled_blocks_per_cu(bool wide)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled, kTPB, 0) !=
-            hipSuccess ||
-        nb < 1)
+    const hipError_t e =
+        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled_512,
+                                                            kTPBWide, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled,
+                                                            kTPB, 0);
+    if (e != hipSuccess || nb < 1)
         nb = 1;
     return nb;
 }
@@ -924,7 +963,7 @@ k_bitset_pass(const InstDev *inst, int pass, Tables tb,
         __syncthreads();
         uint32_t Phi, Plo;
         prefix_planes(t, pl, Phi, Plo);
-        marks += mark_string(I, seq, Phi, Plo, premask, sh, tb);
+        marks += mark_string<kTPB>(I, seq, Phi, Plo, premask, sh, tb);
         passes++;
         unsigned long long *Ag = A + t * (uint64_t)W;
         int nz = 0;
@@ -967,7 +1006,7 @@ k_bitset_count(const InstDev *inst, const unsigned long long *A,
             for (int w = threadIdx.x; w < W; w += kTPB)
                 c += __popcll(Ag[w]);
         }
-        c = block_sum64(c, red);
+        c = block_sum64<kTPB>(c, red);
         if (threadIdx.x == 0)
             tile_cnt[t] = (uint32_t)c;
     }
@@ -1000,7 +1039,7 @@ k_bitset_emit(const InstDev *inst, const unsigned long long *A,
         __syncthreads();
         const uint64_t pos = tile_pos[t];
         const bool fits = pos + tile_cnt[t] <= cap;
-        emit_words(sh, W, t, I.s, out + (fits ? pos : 0), fits, sh.red32);
+        emit_words<kTPB>(sh, W, t, I.s, out + (fits ? pos : 0), fits, sh.red32);
         __syncthreads();
     }
 }

@@ -581,10 +581,14 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         } else if (P.path == PMS_PATH_TILED) {
             const uint64_t max_items = 1u << 20;
             uint64_t chunk = (ntiles + max_items - 1) / max_items;
+            // tiles of 4^9 codes on the plain path: the 512-thread kernel
+            // (twice the waves per CU in flight)
+            const bool wide = !quorum && P.s == kMaxSuffix;
+            const int tgrid =
+                grid_for(c, wide ? c->tiled_wide_bpc : c->tiled_bpc);
             // sibling tiles share one string order: items of kOrderReuse
             // tiles where that still leaves every workgroup many items
-            const uint64_t grid_tiles =
-                (uint64_t)grid_for(c, c->tiled_bpc) * kOrderReuse * 4;
+            const uint64_t grid_tiles = (uint64_t)tgrid * kOrderReuse * 4;
             if (!quorum && I.tile_order && ntiles >= grid_tiles)
                 chunk = std::max<uint64_t>(chunk, kOrderReuse);
             const uint64_t nitems = (ntiles + chunk - 1) / chunk;
@@ -596,8 +600,9 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             else
                 HIPCHK(c, launch_tiled(d_inst, nullptr, (int)nitems, chunk,
                                        (unsigned int *)d_next, c->tb, d_stats,
-                                       grid_for(c, c->tiled_bpc), st));
+                                       tgrid, st, wide));
             S.main_launches = 1;
+            S.tile_threads = wide ? 512 : 256;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
             HIPCHK(c, launch_scan_u32(I.tile_cnt, ntiles, tile_pos,
                                       base + lay.scan, st));
@@ -799,6 +804,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     }
     c->n_cu = prop.multiProcessorCount;
     c->tiled_bpc = tiled_blocks_per_cu();
+    c->tiled_wide_bpc = tiled_blocks_per_cu(true);
     c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
     c->alpha_bpc = alpha_blocks_per_cu();
     c->pair_bpc = pair_blocks_per_cu();

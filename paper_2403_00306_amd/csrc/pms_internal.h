@@ -132,10 +132,12 @@ hipError_t launch_index(const InstDev *d_insts, int ninst, int max_rows_words,
 
 // Tiled pattern-driven kernel over a work list (persistent workgroups).
 // d_items == nullptr: instance 0's tiles in nitems chunks of `chunk`.
+// wide: the 512-thread kernel (for tiles of 4^9 codes on the plain path)
 hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
                         int nitems, uint64_t chunk, unsigned int *d_next,
-                        Tables tb, TileStats *stats, int grid, hipStream_t st);
-int tiled_blocks_per_cu();
+                        Tables tb, TileStats *stats, int grid, hipStream_t st,
+                        bool wide = false);
+int tiled_blocks_per_cu(bool wide = false);
 // Any-alphabet sample-driven filter (k_alpha.hip).
 struct AlphaJob {
     const uint8_t *letters;      // n*m letter codes (index in the alphabet)

@@ -30,6 +30,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.hip",
+                  "k_tiled_512": "csrc/k_tiles.hip",
                   "k_tiled_quorum": "csrc/k_tiles.hip",
                   "k_alpha_filter": "csrc/k_alpha.hip",
                   "k_pair_filter": "csrc/k_pair.hip",
