@@ -114,10 +114,17 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         // work items: chunks of tiles sized so that one item costs about
         // 1/8 of a persistent workgroup's share, most expensive first (a
         // long item at the end would leave the rest of the chip idle)
-        double total_cost = 0;
-        for (auto &b : mem)
+        double total_cost = 0, wide_cost = 0;
+        for (auto &b : mem) {
             total_cost += b.cost;
-        const double slots = (double)std::max(1, c->n_cu * c->tiled_bpc);
+            if (b.s == kMaxSuffix)
+                wide_cost += b.cost;
+        }
+        // the 512-thread tile kernel when most of the work is in tiles of
+        // 4^9 codes (it is faster there and about even elsewhere)
+        const bool wide = wide_cost >= 0.5 * total_cost;
+        const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
+        const double slots = (double)std::max(1, c->n_cu * tbpc);
         const double target = total_cost / (slots * 8.0);
         std::vector<WorkItem> items;
         std::vector<double> icost;
@@ -282,8 +289,8 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
             if (ce == hipSuccess)
                 ce = launch_tiled(d_desc, d_items, (int)witems.size(), 0,
                                   (unsigned int *)(base + o_next), c->tb,
-                                  d_stats,
-                                  std::max(1, c->n_cu * c->tiled_bpc), st);
+                                  d_stats, std::max(1, c->n_cu * tbpc), st,
+                                  wide);
             if (ce == hipSuccess)
                 ce = launch_scan_u32((uint32_t *)(base + o_cnt), tile_total,
                                      tile_pos, base + o_scan, st);

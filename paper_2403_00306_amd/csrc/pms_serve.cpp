@@ -315,7 +315,7 @@ void Server::run()
         const double budget = kLaunchTargetMs * ops_per_ms;
         const double share = budget / (double)act.size();
         size_t ni = 0;
-        double planned = 0;
+        double planned = 0, planned_wide = 0;
         std::vector<uint64_t> took(act.size(), 0);
         for (size_t a = 0; a < act.size() && rc == PMS_OK; a++) {
             Req *r = act[a];
@@ -339,15 +339,21 @@ void Server::run()
             }
             took[a] = t - r->next_tile;
             planned += (double)took[a] * r->cost_per_tile;
+            if (r->s == kMaxSuffix)
+                planned_wide += (double)took[a] * r->cost_per_tile;
         }
         if (rc == PMS_OK && ni > 0) {
+            // the 512-thread tile kernel when most of this launch's work is
+            // in tiles of 4^9 codes
+            const bool wide = planned_wide >= 0.5 * planned;
+            const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
             if (hipMemcpyAsync(d_items, h_items, sizeof(WorkItem) * ni,
                                hipMemcpyHostToDevice, st) != hipSuccess ||
                 launch_fill_u32(d_next, 1, 0, st) != hipSuccess ||
                 hipEventRecord(e0, st) != hipSuccess ||
                 launch_tiled(d_slots, d_items, (int)ni, 0, d_next, c->tb,
-                             nullptr, std::max(1, c->n_cu * c->tiled_bpc),
-                             st) != hipSuccess ||
+                             nullptr, std::max(1, c->n_cu * tbpc), st,
+                             wide) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 rc = PMS_EDEVICE;
