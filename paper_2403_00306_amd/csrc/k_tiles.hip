@@ -503,11 +503,18 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         const unsigned long long mk = mark_string<TPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         unsigned long long cnt = 0;
+        // word tid + k*kTPB sits at wpos(tid) ^ wpos(k*kTPB) (wpos is
+        // XOR-linear, the two parts share no bits); the base is made opaque
+        // per pass so that the compiler does not hold one address per word
+        // across the pass loop (at 64 VGPRs it spilled them to scratch)
+        uint32_t tw = (uint32_t)tid;
+        asm volatile("" : "+v"(tw));
+        const uint32_t pbase = wpos(tw);
 #pragma unroll
         for (int k = 0; k < kWordsPerThread; k++) {
             const int w = tid + k * kTPB;
             if (w < W) {
-                const uint32_t pw = wpos((uint32_t)w);
+                const uint32_t pw = pbase ^ wpos((uint32_t)(k * kTPB));
                 // read and clear in one LDS instruction
                 const unsigned long long u = __hip_atomic_exchange(
                     &sh.U[pw], 0ull, __ATOMIC_RELAXED,
