@@ -745,11 +745,15 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
         const unsigned long long mk = mark_string<kTPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         int nz = 0;
+        // per-pass word addresses from an opaque tid (see run_tile)
+        uint32_t tw = (uint32_t)tid;
+        asm volatile("" : "+v"(tw));
+        const uint32_t pbase = wpos(tw);
 #pragma unroll
         for (int k = 0; k < kQWords; k++) {
             const int w = tid + k * kTPB;
             if (w < W) {
-                const uint32_t pw = wpos((uint32_t)w);
+                const uint32_t pw = pbase ^ wpos((uint32_t)(k * kTPB));
                 const unsigned long long u = sh.U[pw];
                 sh.U[pw] = 0;
                 // add 1 to the count of every live code outside U
@@ -851,7 +855,15 @@ __device__ __forceinline__ void drain_items(const InstDev *insts,
             w.t0 = (uint64_t)it * chunk;
             w.t1 = min(w.t0 + chunk, insts[0].ntiles);
         }
-        const InstDev I = insts[w.inst];
+        w.inst = uni(w.inst);
+        w.t0 = uni((unsigned long long)w.t0);
+        w.t1 = uni((unsigned long long)w.t1);
+        // the descriptor in scalar registers: it removed the VGPR spills of
+        // the 512-thread and quorum kernels; the plain 256-thread kernel
+        // has none and only gained SGPR spills from it
+        const InstDev I = (TPB >= kTPBWide || Quorum)
+                              ? uni_desc(insts[w.inst])
+                              : insts[w.inst];
         for (uint64_t t = w.t0; t < w.t1; t++) {
             if (Quorum)
                 run_tile_quorum(I, t, sh, tb, acc);

@@ -95,6 +95,24 @@ struct InstDev {
     int tile_order;          // tiled path: order the strings per tile
 };
 
+// The descriptor read by every thread of a workgroup is the same: make each
+// of its words wave-uniform so that its fields live in scalar registers
+// (loaded through a vector register they would hold a VGPR pair per
+// pointer, which the 512-thread tile kernel spilled).
+__device__ __forceinline__ InstDev uni_desc(const InstDev &x)
+{
+    static_assert(sizeof(InstDev) % 4 == 0, "descriptor words");
+    constexpr int kW = (int)(sizeof(InstDev) / 4);
+    uint32_t wd[kW];
+    __builtin_memcpy(wd, &x, sizeof(InstDev));
+#pragma unroll
+    for (int i = 0; i < kW; i++)
+        wd[i] = __builtin_amdgcn_readfirstlane(wd[i]);
+    InstDev y;
+    __builtin_memcpy(&y, wd, sizeof(InstDev));
+    return y;
+}
+
 // A contiguous range of one instance's tiles.
 struct WorkItem {
     int inst;
