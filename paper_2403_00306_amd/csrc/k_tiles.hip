@@ -178,7 +178,7 @@ __device__ __forceinline__ void or64_at(TileShared &sh, uint32_t off,
 // sphere in registers and walks the class's l-mers. When the sphere has
 // more than kTPB/2 entries every wave walks the same l-mers (64 read at
 // once, then broadcast into scalar registers by readlane); a smaller
-// sphere is repeated in 256/bs lane groups that walk different l-mers.
+// sphere is repeated in kTPB/bs lane groups that walk different l-mers.
 template <int TPB>
 __device__ unsigned long long mark_string(const InstDev &I, int seq,
                                           uint32_t Phi, uint32_t Plo,
@@ -248,7 +248,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
             // class leaves idle fall in a different wave each time
             const uint32_t rot = 64u * (uint32_t)r;
             if (bs > (uint32_t)kTPB / 2) {
-                // Entry-parallel: lane owns entries e, e+256, ... of the
+                // Entry-parallel: lane owns entries e, e+kTPB, ... of the
                 // sphere and the wave walks the class's l-mers, 64 at a
                 // time: one LDS read per lane, then broadcast by readlane.
                 // Every lane of a working wave stays active (readlane needs
@@ -319,7 +319,7 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     }
                 }
             } else {
-                // G = 256/bs groups of bs lanes: each lane owns one entry
+                // G = kTPB/bs groups of bs lanes: each lane owns one entry
                 // and its group walks every G-th l-mer of the class
                 const uint32_t vt = ((uint32_t)tid + rot) & (uint32_t)(kTPB - 1);
                 const uint32_t G = (uint32_t)kTPB / bs;
