@@ -524,10 +524,10 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             }
         }
         total = block_sum64<TPB>(cnt, sh.red64);
-        if (tid == 0) {
-            acc.passes++;
-            acc.marks += mk;
-        }
+        // work counters: every thread adds the same (uniform) amounts, so
+        // they stay in scalar registers (thread 0 flushes them at the end)
+        acc.passes++;
+        acc.marks += mk;
         if (total == 0)
             break;
         if (total <= (unsigned long long)I.surv_t && si + 1 < I.n) {
@@ -535,8 +535,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
             break;
         }
     }
-    if (tid == 0)
-        acc.tiles++;
+    acc.tiles++;
     if (total == 0) {
         if (tid == 0) {
             tile_cnt[g] = 0;
@@ -631,8 +630,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     __syncthreads();   // the list is complete
     int cur = 0;
     for (int sj = si + 1; sj < I.n && N > 0; sj++) {
-        if (tid == 0)
-            acc.ftests += (unsigned long long)N * (unsigned long long)L;
+        acc.ftests += (unsigned long long)N * (unsigned long long)L;
         const uint2 *plc = cur ? plb1 : plb0;
         const uint64_t *cdc = cur ? cdb1 : sh.surv;
         for (int r = 0; r < rounds; r++) {
@@ -779,17 +777,16 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
                 nz |= live[k] != 0;
             }
         }
-        if (tid == 0) {
-            acc.passes++;
-            acc.marks += mk;
-        }
+        // work counters: every thread adds the same (uniform) amounts, so
+        // they stay in scalar registers (thread 0 flushes them at the end)
+        acc.passes++;
+        acc.marks += mk;
         if (!__syncthreads_or(nz)) {
             any = false;
             break;
         }
     }
-    if (tid == 0)
-        acc.tiles++;
+    acc.tiles++;
     if (!any) {
         if (tid == 0) {
             I.tile_cnt[t] = 0;
