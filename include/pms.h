@@ -90,6 +90,10 @@ typedef struct {
                                  once; 0 = 64 */
     int serve_queue;          /* serving: max requests waiting for
                                  admission; 0 = 4096 */
+    int tile_threads;         /* tiled path: workgroup size of the tile
+                                 kernel, 256 or 512; 0 = automatic (512
+                                 where the tiles hold 4^9 codes). The
+                                 result does not depend on it. */
 } pms_options;
 
 /* Fill *opt with the defaults above (device 0, auto path). */

@@ -583,7 +583,8 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             uint64_t chunk = (ntiles + max_items - 1) / max_items;
             // tiles of 4^9 codes on the plain path: the 512-thread kernel
             // (twice the waves per CU in flight)
-            const bool wide = !quorum && P.s == kMaxSuffix;
+            const bool wide =
+                !quorum && pick_wide(c, P.s == kMaxSuffix);
             const int tgrid =
                 grid_for(c, wide ? c->tiled_wide_bpc : c->tiled_bpc);
             // sibling tiles share one string order: items of kOrderReuse
@@ -783,7 +784,9 @@ int pms_create(pms_ctx **out, const pms_options *opt)
         return PMS_EINVAL;
     }
     if (o.path < 0 || o.path > PMS_PATH_PAIR || o.serve_slots < 0 ||
-        o.serve_queue < 0) {
+        o.serve_queue < 0 ||
+        (o.tile_threads != 0 && o.tile_threads != 256 &&
+         o.tile_threads != 512)) {
         g_create_error = "bad option value";
         return PMS_EINVAL;
     }

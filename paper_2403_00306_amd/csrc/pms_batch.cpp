@@ -122,7 +122,7 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         }
         // the 512-thread tile kernel when most of the work is in tiles of
         // 4^9 codes (it is faster there and about even elsewhere)
-        const bool wide = wide_cost >= 0.5 * total_cost;
+        const bool wide = pick_wide(c, wide_cost >= 0.5 * total_cost);
         const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
         const double slots = (double)std::max(1, c->n_cu * tbpc);
         const double target = total_cost / (slots * 8.0);

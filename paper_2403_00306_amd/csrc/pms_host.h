@@ -63,6 +63,10 @@ struct Plan {
     double cost_filter, cost_tiled;
 };
 
+// Tile kernel workgroup size: the caller's choice (pms_options.tile_threads)
+// or, when that is 0, the automatic one.
+inline bool pick_wide(const pms_ctx *c, bool automatic);
+
 struct SolveOut {
     uint64_t *d_out;
     size_t count;
@@ -137,6 +141,12 @@ struct pms_ctx {
     } while (0)
 
 namespace pms {
+
+inline bool pick_wide(const pms_ctx *c, bool automatic)
+{
+    return c->opt.tile_threads == 512 ||
+           (c->opt.tile_threads == 0 && automatic);
+}
 // q = 0 (or q = n): plain PMS; 1 <= q < n: (l,d,q)-motifs (tiled path).
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,

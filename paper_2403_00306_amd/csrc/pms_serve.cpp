@@ -345,7 +345,7 @@ void Server::run()
         if (rc == PMS_OK && ni > 0) {
             // the 512-thread tile kernel when most of this launch's work is
             // in tiles of 4^9 codes
-            const bool wide = planned_wide >= 0.5 * planned;
+            const bool wide = pick_wide(c, planned_wide >= 0.5 * planned);
             const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
             if (hipMemcpyAsync(d_items, h_items, sizeof(WorkItem) * ni,
                                hipMemcpyHostToDevice, st) != hipSuccess ||

@@ -229,6 +229,38 @@ def test_tile_shapes_do_not_change_result():
                 assert c.stats()["tile_suffix"] == s
 
 
+@pytest.mark.parametrize("threads", [256, 512])
+def test_tile_kernel_sizes_vs_oracle(threads):
+    # both workgroup sizes of the tile kernel, forced, on every tile suffix
+    # (the automatic choice takes 512 threads only for s = 9)
+    inst = pmsgen.planted(5, 12, 300, 11, 3)
+    want = oracle_set(inst.seqs, inst.n, inst.m, 11, 3)
+    with pms.Context(path=pms.PATH_TILED, tile_threads=threads) as c:
+        for s in (3, 6, 8, 9):
+            for t in (1, 64, 256):
+                c.set_tile_config(11, 3, s, t)
+                got = c.solve(inst.seqs, inst.n, inst.m, 11, 3)
+                np.testing.assert_array_equal(
+                    got, want, err_msg="threads=%d s=%d t=%d" % (threads, s, t))
+                assert c.stats()["tile_threads"] == threads
+
+
+def test_tile_kernel_sizes_agree_17_6():
+    inst = pmsgen.plain("pms_17_6", 1)
+    res = {}
+    for threads in (0, 256, 512):
+        with pms.Context(path=pms.PATH_TILED, tile_threads=threads) as c:
+            res[threads] = c.solve(inst.seqs, 20, 600, 17, 6)
+            st = c.stats()
+        say("(17,6) threads", threads, "->", st["tile_threads"], "ms",
+            st["ms_main"])
+        assert st["tile_threads"] == (threads or 512)
+    np.testing.assert_array_equal(res[256], res[512])
+    np.testing.assert_array_equal(res[0], res[512])
+    with pytest.raises(pms.PmsError):
+        pms.Context(tile_threads=128)
+
+
 def test_tile_order_and_long_strings():
     # s = 9 turns the per-tile string order on (a pass's word marks well
     # above the n*L prefix tests) and L = 990 takes the survivor stage over
