@@ -711,14 +711,17 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
 // U as on the plain path and every live code outside U counts one more miss.
 // The tile stops when no code is live; after the last string the live codes
 // are exactly the (l,d,q)-motifs of the tile.
-constexpr int kQWords = (1 << (2 * (kQuorumMaxSuffix - 3))) / kTPB;
+constexpr int kQTileWords = 1 << (2 * (kQuorumMaxSuffix - 3));
 constexpr int kQPlanes = 5;   // counts 0..kQuorumMaxMiss + 1
-static_assert(kQWords >= 1 && (kQuorumMaxMiss + 1) < (1 << kQPlanes),
+static_assert(kQTileWords >= kTPBWide && (kQuorumMaxMiss + 1) < (1 << kQPlanes),
               "quorum counters");
 
+template <int TPB>
 __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
                                 const Tables &tb, StatAcc &acc)
 {
+    constexpr int kTPB = TPB;
+    constexpr int kQWords = kQTileWords / TPB;   // words per thread
     const int tid = threadIdx.x;
     const int s = I.s, q = s - 3, pl = I.l - s;
     const int W = 1 << (2 * q);
@@ -740,7 +743,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
     bool any = true;
     for (int si = 0; si < I.n; si++) {
         const int seq = uni(I.order[si]);
-        const unsigned long long mk = mark_string<kTPB>(I, seq, Phi, Plo, premask,
+        const unsigned long long mk = mark_string<TPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
         int nz = 0;
         // per-pass word addresses from an opaque tid (see run_tile)
@@ -803,7 +806,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
             cnt += __popcll(live[k]);
         }
     }
-    const unsigned long long total = block_sum64<kTPB>(cnt, sh.red64);
+    const unsigned long long total = block_sum64<TPB>(cnt, sh.red64);
     if (tid == 0) {
         const unsigned long long off = atomicAdd(I.heap_top, total);
         sh.bcast = off;
@@ -813,7 +816,7 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
     __syncthreads();
     const unsigned long long off = uni(sh.bcast);
     const bool fits = off + total <= I.heap_cap;
-    emit_words<kTPB>(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
+    emit_words<TPB>(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
     __syncthreads();
     for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
         sh.U[w] = 0;
@@ -863,7 +866,7 @@ __device__ __forceinline__ void drain_items(const InstDev *insts,
                               : insts[w.inst];
         for (uint64_t t = w.t0; t < w.t1; t++) {
             if (Quorum)
-                run_tile_quorum(I, t, sh, tb, acc);
+                run_tile_quorum<TPB>(I, t, sh, tb, acc);
             else
                 run_tile<TPB>(I, t, sh, tb, acc,
                          (t != w.t0 && (t & (uint64_t)(kOrderReuse - 1)) != 0)
@@ -895,12 +898,17 @@ k_tiled_512(const InstDev *insts, const WorkItem *items, int nitems,
                                  stats);
 }
 
-__global__ __launch_bounds__(kTPB, 4) void
+// 256 threads: at 512 the bit-sliced counters no longer fit 64 VGPRs
+// without spills in the pass loop (measured 1.5x slower)
+constexpr int kQuorumTPB = kTPB;
+
+__global__ __launch_bounds__(kQuorumTPB, kQuorumTPB / 64) void
 k_tiled_quorum(const InstDev *insts, const WorkItem *items, int nitems,
                uint64_t chunk, unsigned int *next, Tables tb,
                TileStats *stats)
 {
-    drain_items<kTPB, true>(insts, items, nitems, chunk, next, tb, stats);
+    drain_items<kQuorumTPB, true>(insts, items, nitems, chunk, next, tb,
+                                  stats);
 }
 
 hipError_t launch_tiled(const InstDev *d_insts, const WorkItem *d_items,
@@ -926,7 +934,7 @@ hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,
 {
     if (nitems <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_tiled_quorum, dim3(grid), dim3(kTPB), 0, st,
+    hipLaunchKernelGGL(k_tiled_quorum, dim3(grid), dim3(kQuorumTPB), 0, st,
                        d_insts, d_items, nitems, chunk, d_next, tb, stats);
     return hipGetLastError();
 }
@@ -935,7 +943,7 @@ int tiled_quorum_blocks_per_cu()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiled_quorum,
-                                                     kTPB, 0) != hipSuccess ||
+                                                     kQuorumTPB, 0) != hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;
