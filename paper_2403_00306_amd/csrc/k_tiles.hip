@@ -257,6 +257,14 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 // the previous round, already ORs; ORs are idempotent.
                 const uint32_t wfirst =
                     uni(((uint32_t)tid - lane + rot) & (uint32_t)(kTPB - 1));
+                // a class of at most 64 l-mers (nearly all) is read once for
+                // all its rounds: every LDS read waits for the wave's
+                // earlier ORs to complete
+                int v1 = 0;
+                if (c <= 64 && wfirst < bs) {
+                    const int vl = (int)yl[min((int)lane, c - 1)];
+                    asm volatile("v_mov_b32 %0, %1" : "=v"(v1) : "v"(vl));
+                }
                 for (uint32_t eb = 0; eb < bs; eb += kTPB) {
                     const uint32_t e0 = wfirst + eb;
                     if (e0 >= bs)
@@ -270,13 +278,16 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     const bool single = __ballot(tt != 0) == 0;
                     for (int y0c = 0; y0c < c; y0c += 64) {
                         const int nc = min(64, c - y0c);
-                        const int vl =
-                            (int)yl[y0c + min((int)lane, nc - 1)];
-                        // a VALU copy: the LDS read is waited for here,
-                        // once, and not at every readlane below (where a
-                        // wait would also drain this wave's pending ORs)
-                        int v;
-                        asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"(vl));
+                        int v = v1;
+                        if (c > 64) {
+                            const int vl =
+                                (int)yl[y0c + min((int)lane, nc - 1)];
+                            // a VALU copy: the LDS read is waited for here,
+                            // once, and not at every readlane below (where
+                            // a wait would also drain this wave's pending
+                            // ORs)
+                            asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"(vl));
+                        }
                         int j = 0;
                         if (single) {
                             // in-word radius 0 in the whole wave: the word
