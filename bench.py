@@ -27,6 +27,9 @@ PEAK_HBM = 8.0e12                   # bytes/s
 #  tile prefix test: xor + bitop3 + and + bcnt, compare folded = 4
 #  word-level sphere mark: word index xor + the OR itself = 2
 OPS_TEST = 3.5
+# the calibration kernel's loop body as compiled for gfx950: per 128 tests
+# 128 v_xor, 128 v_bitop3, 128 v_bcnt, 64 v_min and 32 v_min3
+VALU_PER_TEST_CAL = 480.0 / 128.0
 OPS_PREFIX = 4.0
 OPS_MARK = 2.0
 # any-alphabet filter, per Hamming test on 5 bit planes
@@ -70,6 +73,65 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def single_thread_oracle(pmsgen) -> dict:
+    """The oracle on one thread: all of (9,2) and the first 30 reference
+    l-mers of (13,4) (n = 20, m = 600, seed 1)."""
+    import oracle
+    out = {}
+    for name, l, d, refs in (("pms_9_2", 9, 2, None), ("pms_13_4", 13, 4, 30)):
+        inst = pmsgen.plain(name, 1)
+        L = inst.m - l + 1
+        k = L if refs is None else min(refs, L)
+        t0 = time.perf_counter()
+        _, h = oracle.o1(inst.seqs, inst.n, inst.m, l, d, 0, k, 1)
+        t = time.perf_counter() - t0
+        out[name] = {"tests_per_s": h / t, "seconds": t, "tests": int(h),
+                     "references": "%d of %d" % (k, L)}
+    return out
+
+
+def seeds_bench(pms, pmsgen, np) -> dict:
+    """(17,6), n = 20, m = 600, seeds 1..5: wall time of pms_solve from host
+    bytes to the host sorted set on a warm context, median of 3 (tiled path,
+    with its kernel time), and one filter-path solve per seed."""
+    res = {}
+    tctx = pms.Context(device=0, path=pms.PATH_TILED)
+    fctx = pms.Context(device=0, path=pms.PATH_FILTER)
+    for seed in range(1, 6):
+        inst = pmsgen.planted(seed, 20, 600, 17, 6)
+        tctx.solve(inst.seqs, 20, 600, 17, 6)            # warm
+        walls, kms = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            got = tctx.solve(inst.seqs, 20, 600, 17, 6)
+            walls.append((time.perf_counter() - t0) * 1000.0)
+            kms.append(tctx.stats()["ms_main"])
+        t0 = time.perf_counter()
+        fgot = fctx.solve(inst.seqs, 20, 600, 17, 6)
+        fwall = (time.perf_counter() - t0) * 1000.0
+        assert np.array_equal(got, fgot), "paths disagree at seed %d" % seed
+        res["seed_%d" % seed] = {
+            "tiled_solve_ms": float(np.median(walls)),
+            "tiled_kernel_ms": float(np.median(kms)),
+            "filter_solve_ms": fwall,
+            "filter_kernel_ms": fctx.stats()["ms_main"],
+            "motifs": int(len(got))}
+    tctx.close()
+    fctx.close()
+    log("seeds: " + json.dumps(res))
+    return res
+
+
 def cpu_baseline(inst, target_s: float = 12.0) -> dict:
     """The oracle as it stands, on a bounded sample of reference l-mers."""
     import oracle
@@ -88,7 +150,7 @@ def cpu_baseline(inst, target_s: float = 12.0) -> dict:
     _, h = oracle.o1(inst.seqs, n, m, l, d, 0, k, threads)
     t = time.perf_counter() - t0
     return {"value": h / t, "unit": "Hamming tests/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "sample-driven oracle over the first %d of %d reference "
                       "l-mers of s_1 (same instance), %.1f s, %d tests"
                       % (k, L, t, h)}
@@ -449,6 +511,20 @@ def main():
                          "traffic": measured_traffic("k_bitset_pass"),
                          "algorithmic_bytes": bst["bytes_main"]}}
         bctx.close()
+        # the filter's Hamming-test mix at full occupancy from registers:
+        # a check of the derived integer peak the roofline figures use
+        cal = pms.Context(device=0)
+        rate = cal.test_rate()
+        cal.close()
+        extra["alu_calibration"] = {
+            "tests_per_s": rate,
+            "valu_per_test_in_loop": VALU_PER_TEST_CAL,
+            "valu_lane_ops_per_s": rate * VALU_PER_TEST_CAL,
+            "derived_peak_ops_per_s": PEAK_ALU_OPS,
+            "frac_of_derived_peak": rate * VALU_PER_TEST_CAL / PEAK_ALU_OPS}
+        log("alu calibration: %.4g tests/s, %.3g of the derived peak"
+            % (rate, extra["alu_calibration"]["frac_of_derived_peak"]))
+        extra["seeds_17_6"] = seeds_bench(pms, pmsgen, np)
         extra["quorum"] = quorum_bench(pms, pmsgen, np, torch, dev)
         extra["pair_path"] = pair_bench(pms, inst, np)
         extra["protein"] = protein_bench(pms, pmsgen, np)
@@ -466,6 +542,8 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         cpu = cpu_baseline(inst)
+        if not args.no_extra:
+            cpu["single_thread"] = single_thread_oracle(pmsgen)
         log("cpu %.4g tests/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     rec = {"metric": "Hamming tests/s", "value": value,

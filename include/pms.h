@@ -239,6 +239,13 @@ int pms_ticket_times(pms_ctx *ctx, uint64_t ticket, double *t_submit_ms,
 /* Milliseconds on the steady clock used by pms_ticket_times. */
 double pms_clock_ms(void);
 
+/* Calibration, not part of any solve: the device's rate of the Hamming
+ * test of Sec. 3.3.1 as the filter computes it (XOR, OR, popcount, running
+ * minimum over two bit planes), at full occupancy from registers only.
+ * *tests_per_s receives the rate. Runs a kernel of tens of milliseconds on
+ * the context's stream. Returns PMS_EINVAL for NULL arguments. */
+int pms_test_rate(pms_ctx *ctx, double *tests_per_s);
+
 /* Timing and work counters of the last pms_solve / pms_solve_device /
  * pms_solve_batch call. Kernel times come from HIP events recorded on the
  * stream each kernel ran on. */

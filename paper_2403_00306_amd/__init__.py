@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "pms_ticket_times": (i, [vp, u64, P(ctypes.c_double),
                                  P(ctypes.c_double), P(ctypes.c_double)]),
         "pms_clock_ms": (ctypes.c_double, []),
+        "pms_test_rate": (i, [vp, P(ctypes.c_double)]),
         "pms_last_stats": (i, [vp, P(Stats)]),
         "pms_serve_stats_get": (i, [vp, P(ServeStats)]),
         "pms_last_hcanon_per_ref": (i, [vp, P(ctypes.c_uint64), sz]),
@@ -380,6 +381,13 @@ class Context:
 
     def clock_ms(self) -> float:
         return float(self._lib.pms_clock_ms())
+
+    def test_rate(self) -> float:
+        """Hamming tests/s of the filter's instruction mix on this device
+        (calibration of the integer peak; runs a short kernel)."""
+        r = ctypes.c_double(0.0)
+        self._check(self._lib.pms_test_rate(self._h, ctypes.byref(r)))
+        return float(r.value)
 
     def serve_stats(self) -> dict:
         s = ServeStats()

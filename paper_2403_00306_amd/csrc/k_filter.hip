@@ -346,4 +346,77 @@ int filter_blocks_per_cu()
     return nb;
 }
 
+// ---- calibration: the Hamming-test instruction mix at full occupancy ----
+// Each thread holds kCalCand candidates and kCalY l-mers in registers and
+// takes the minimum distance of every candidate to every l-mer, `iters`
+// times over (the l-mers made opaque per round so that no round can be
+// folded away). A test is the filter's: v_xor, v_bitop3 (xor + or), v_bcnt
+// and half a v_min3, i.e. 3.5 VALU ops; nothing else runs in the loop.
+constexpr int kCalCand = 8, kCalY = 16;
+
+__global__ __launch_bounds__(kTPB) void
+k_test_rate(int iters, uint32_t seed, unsigned int *sink)
+{
+    uint32_t cx[kCalCand], cy[kCalCand], yx[kCalY], yy[kCalY];
+    const uint32_t g = blockIdx.x * kTPB + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kCalCand; k++) {
+        cx[k] = (g + (uint32_t)k) * 0x9E3779B9u ^ seed;
+        cy[k] = (g ^ (uint32_t)k) * 0x85EBCA6Bu;
+    }
+#pragma unroll
+    for (int j = 0; j < kCalY; j++) {
+        yx[j] = (uint32_t)j * 0xC2B2AE35u ^ seed;
+        yy[j] = (uint32_t)j * 0x27D4EB2Fu;
+    }
+    uint32_t mind[kCalCand];
+#pragma unroll
+    for (int k = 0; k < kCalCand; k++)
+        mind[k] = 255;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int j = 0; j < kCalY; j++)
+            asm volatile("" : "+v"(yx[j]), "+v"(yy[j]));
+#pragma unroll
+        for (int j = 0; j < kCalY; j += 2) {
+#pragma unroll
+            for (int k = 0; k < kCalCand; k++) {
+                const uint32_t h0 = __popc((cx[k] ^ yx[j]) | (cy[k] ^ yy[j]));
+                const uint32_t h1 =
+                    __popc((cx[k] ^ yx[j + 1]) | (cy[k] ^ yy[j + 1]));
+                mind[k] = min(mind[k], min(h0, h1));
+            }
+        }
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kCalCand; k++)
+        acc += mind[k];
+    if (acc == 0xFFFFFFFFu)   // never true; keeps the work observable
+        atomicAdd(sink, acc);
+}
+
+hipError_t launch_test_rate(int grid, int iters, uint32_t seed,
+                            unsigned int *sink, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_test_rate, dim3(grid), dim3(kTPB), 0, st, iters,
+                       seed, sink);
+    return hipGetLastError();
+}
+
+int test_rate_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_test_rate, kTPB,
+                                                     0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+uint64_t test_rate_tests_per_thread(int iters)
+{
+    return (uint64_t)iters * (uint64_t)(kCalCand * kCalY);
+}
+
 }  // namespace pms

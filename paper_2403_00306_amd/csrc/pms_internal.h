@@ -269,6 +269,11 @@ hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
                          unsigned long long *hc_per_ref, int grid,
                          hipStream_t st);
 int filter_blocks_per_cu();
+// calibration kernel: the filter's Hamming-test mix from registers only
+hipError_t launch_test_rate(int grid, int iters, uint32_t seed,
+                            unsigned int *sink, hipStream_t st);
+int test_rate_blocks_per_cu();
+uint64_t test_rate_tests_per_thread(int iters);
 
 // Scans, ordered gathers and sorting (a6).
 size_t scan_scratch_bytes(uint64_t n);

@@ -151,3 +151,35 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
         *best_t = pick.second;
     return PMS_OK;
 }
+
+// Rate of the Hamming-test instruction mix on this device at full
+// occupancy, from registers only (a check of the integer peak that the
+// roofline figures assume).
+extern "C" int pms_test_rate(pms_ctx *c, double *tests_per_s)
+{
+    if (!c || !tests_per_s)
+        return PMS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = c->alloc(c->aux, 256);
+    if (rc)
+        return rc;
+    const hipStream_t st = c->stream;
+    const int grid = std::max(1, c->n_cu * test_rate_blocks_per_cu());
+    unsigned int *sink = (unsigned int *)c->aux.p;
+    HIPCHK(c, launch_test_rate(grid, 64, 1u, sink, st));   // warm-up
+    // about 2e11 tests: tens of milliseconds
+    const uint64_t per_iter =
+        (uint64_t)grid * kTPB * test_rate_tests_per_thread(1);
+    const int iters = (int)std::max<uint64_t>(
+        64, std::min<uint64_t>(1u << 20, 200000000000ull / per_iter));
+    HIPCHK(c, hipEventRecord(c->ev[0], st));
+    HIPCHK(c, launch_test_rate(grid, iters, 2u, sink, st));
+    HIPCHK(c, hipEventRecord(c->ev[1], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[1]));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    if (ms <= 0)
+        return c->fail(PMS_EDEVICE, "test rate: no elapsed time");
+    *tests_per_s = (double)per_iter * (double)iters / ((double)ms / 1e3);
+    return PMS_OK;
+}
