@@ -492,7 +492,12 @@ def main():
                    "achieved": f_ops / (fst["ms_main"] / 1000.0) / 1e12,
                    "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
                    "frac": f_ops / (fst["ms_main"] / 1000.0) / PEAK_ALU_OPS,
-                   "traffic": measured_traffic("k_filter")}
+                   "traffic": measured_traffic("k_filter"),
+                   # the tests the kernel executed (whole waves, including
+                   # empty candidate slots) and the same fraction on them
+                   "exec_tests": fst["filter_tests"],
+                   "frac_exec": fst["filter_tests"] * OPS_TEST
+                   / (fst["ms_main"] / 1000.0) / PEAK_ALU_OPS}
     extra = {}
     if not args.no_extra:
         bctx = pms.Context(device=0, path=pms.PATH_BITSET)

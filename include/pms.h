@@ -265,7 +265,11 @@ typedef struct {
     uint64_t marks;           /* tiled/bitset: 64-bit sphere-word ORs */
     uint64_t filter_tests;    /* tiled: Hamming tests of the filter stage;
                                  pair path: tests against s_3..s_n (L per
-                                 string examined) */
+                                 string examined); filter path: tests the
+                                 kernel executed, candidate slots x l-mers
+                                 scanned over whole waves (a wave leaves a
+                                 string once each of its live candidates
+                                 has a hit), beside the canonical hcanon */
     uint64_t bytes_main;      /* bitset path: device bytes read+written */
     uint64_t retries;         /* output-capacity retries */
     uint64_t pairs;           /* pair path: pairs (x, y) with d_H <= 2d */

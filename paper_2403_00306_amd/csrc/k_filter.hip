@@ -133,9 +133,11 @@ struct BRow {
 };
 
 // Minimum distance from each of the thread's first K candidates to the
-// l-mers of one string; the l-mer is the same for the whole wave.
+// l-mers of one string; the l-mer is the same for the whole wave. Returns
+// the number of l-mers the wave tested (it stops once every live candidate
+// has a hit).
 template <int K>
-__device__ __forceinline__ void scan_string(const BRow yp, int L,
+__device__ __forceinline__ int scan_string(const BRow yp, int L,
                                             const uint2 *c, uint32_t *mind,
                                             int d, unsigned int live_mask)
 {
@@ -156,7 +158,7 @@ __device__ __forceinline__ void scan_string(const BRow yp, int L,
         for (int k = 0; k < K; k++)
             done = done && (!((live_mask >> k) & 1u) || mind[k] <= (uint32_t)d);
         if (__all(done))
-            return;
+            return j + 16;
     }
     for (; j < L; j++) {
         const uint2 y = yp[j];
@@ -165,15 +167,19 @@ __device__ __forceinline__ void scan_string(const BRow yp, int L,
             mind[k] = min(mind[k],
                           (uint32_t)__popc((c[k].x ^ y.x) | (c[k].y ^ y.y)));
     }
+    return L;
 }
 
 __global__ __launch_bounds__(kTPB) void
 k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
          unsigned long long *next_block, uint64_t *heap,
          unsigned long long *heap_top, unsigned long long heap_cap,
-         unsigned long long *hc_per_ref)
+         unsigned long long *hc_per_ref, unsigned long long *hexec_out)
 {
     __shared__ FilterShared sh;
+    // tests executed by this thread: K candidate slots x l-mers scanned
+    // (the same in every lane of a wave)
+    unsigned long long hexec = 0;
     const InstDev I = *inst;
     const int tid = threadIdx.x;
     const int L = I.L, d = I.d, l = I.l;
@@ -232,13 +238,18 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
             const int kk = (nlive + kTPB - 1) / kTPB;
             if (__any(live != 0)) {
                 if (kk <= 1)
-                    scan_string<1>(yp, L, c, mind, d, live);
+                    hexec += (unsigned long long)scan_string<1>(
+                        yp, L, c, mind, d, live);
                 else if (kk <= 2)
-                    scan_string<2>(yp, L, c, mind, d, live);
+                    hexec += 2ull * (unsigned long long)scan_string<2>(
+                        yp, L, c, mind, d, live);
                 else if (kk <= 4)
-                    scan_string<4>(yp, L, c, mind, d, live);
+                    hexec += 4ull * (unsigned long long)scan_string<4>(
+                        yp, L, c, mind, d, live);
                 else
-                    scan_string<kFPer>(yp, L, c, mind, d, live);
+                    hexec += (unsigned long long)kFPer *
+                             (unsigned long long)scan_string<kFPer>(
+                                 yp, L, c, mind, d, live);
             }
             unsigned int keep = 0, nk = 0;
 #pragma unroll
@@ -322,17 +333,20 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
                               (unsigned long long)sh.hc[x - x_first]);
         }
     }
+    if (hexec_out && (threadIdx.x & 63) == 0 && hexec)
+        atomicAdd(hexec_out, 64ull * hexec);
 }
 
 hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
                          uint64_t nb, unsigned long long *next_block,
                          uint64_t *heap, unsigned long long *heap_top,
                          unsigned long long heap_cap,
-                         unsigned long long *hc_per_ref, int grid,
-                         hipStream_t st)
+                         unsigned long long *hc_per_ref,
+                         unsigned long long *hexec, int grid, hipStream_t st)
 {
     hipLaunchKernelGGL(k_filter, dim3(grid), dim3(kTPB), 0, st, d_inst, masks,
-                       nb, next_block, heap, heap_top, heap_cap, hc_per_ref);
+                       nb, next_block, heap, heap_top, heap_cap, hc_per_ref,
+                       hexec);
     return hipGetLastError();
 }
 

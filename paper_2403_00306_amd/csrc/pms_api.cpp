@@ -494,6 +494,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             HIPCHK(c, launch_filter(d_inst, (const uint2 *)c->masks.p, nb,
                                     d_next, I.heap, I.heap_top, heap_cap,
                                     (unsigned long long *)c->hc_ref.p,
+                                    &d_stats->ftests,
                                     grid_for(c, c->filter_bpc), st));
             S.main_launches = 1;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
@@ -712,6 +713,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                     h += v;
             }
             S.hcanon = h;
+            S.filter_tests = ts.ftests;   // executed, whole waves
         } else if (P.path != PMS_PATH_PAIR) {
             S.tiles = (P.path == PMS_PATH_TILED) ? ts.tiles : ntiles;
             S.tile_passes = ts.passes;

@@ -266,8 +266,8 @@ hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
                          uint64_t nb, unsigned long long *next_block,
                          uint64_t *heap, unsigned long long *heap_top,
                          unsigned long long heap_cap,
-                         unsigned long long *hc_per_ref, int grid,
-                         hipStream_t st);
+                         unsigned long long *hc_per_ref,
+                         unsigned long long *hexec, int grid, hipStream_t st);
 int filter_blocks_per_cu();
 // calibration kernel: the filter's Hamming-test mix from registers only
 hipError_t launch_test_rate(int grid, int iters, uint32_t seed,

@@ -180,6 +180,11 @@ def test_13_4_more_seeds(seed):
         np.testing.assert_array_equal(got, want)
         if path == pms.PATH_FILTER:
             assert st["hcanon"] == h
+            # executed tests: whole waves (multiples of 64), same order of
+            # magnitude as the canonical count
+            ex = st["filter_tests"]
+            assert ex > 0 and ex % 64 == 0
+            assert 0.2 * h <= ex <= 20 * h, (ex, h)
 
 
 def test_17_6_properties():
