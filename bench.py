@@ -469,7 +469,7 @@ def main():
 
     value = hcanon / (ms_step / 1000.0)
     k_ms = float(np.mean(kms))
-    # dominant kernel of the timed path (k_tiled or, for tiles of 4^9 codes,
+    # dominant kernel of the timed path (k_tiled or, for tiles of 4^8-4^9 codes,
     # its 512-thread form k_tiled_512): algorithmic integer work
     # of one launch from its work counters, over its average HIP-event time
     L = m - l + 1

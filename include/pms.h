@@ -92,8 +92,8 @@ typedef struct {
                                  admission; 0 = 4096 */
     int tile_threads;         /* tiled path: workgroup size of the tile
                                  kernel, 256 or 512; 0 = automatic (512
-                                 where the tiles hold 4^9 codes). The
-                                 result does not depend on it. */
+                                 where the tiles hold 4^8 or 4^9 codes).
+                                 The result does not depend on it. */
 } pms_options;
 
 /* Fill *opt with the defaults above (device 0, auto path). */
@@ -276,7 +276,8 @@ typedef struct {
     uint64_t candidates;      /* pair path: sum of |B(x,d) ∩ B(y,d)| */
     int tile_threads;         /* tiled path (single instance): threads per
                                  workgroup of the tile kernel, 512 for
-                                 tiles of 4^9 codes, else 256; 0 otherwise */
+                                 tiles of 4^8 or 4^9 codes, else 256; 0
+                                 otherwise */
 } pms_stats;
 
 int pms_last_stats(const pms_ctx *ctx, pms_stats *out);

@@ -32,7 +32,7 @@ namespace pms {
 // The tile code is written for a workgroup of TPB threads: kTPB (256, four
 // waves) for every tiled kernel, and kTPBWide (512, eight waves at up to 64
 // VGPRs) for a second plain-path kernel that keeps twice the waves per CU
-// in flight; the planner takes it for tiles of 4^9 codes. Inside the
+// in flight; the planner takes it for tiles of 4^8 and 4^9 codes. Inside the
 // templates kTPB, kWaves and kWordsPerThread are redeclared for TPB.
 constexpr int kTPBWide = 512;
 constexpr int kMaxTileWaves = kTPBWide / 64;

@@ -582,10 +582,11 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         } else if (P.path == PMS_PATH_TILED) {
             const uint64_t max_items = 1u << 20;
             uint64_t chunk = (ntiles + max_items - 1) / max_items;
-            // tiles of 4^9 codes on the plain path: the 512-thread kernel
-            // (twice the waves per CU in flight)
+            // tiles of 4^8 or 4^9 codes on the plain path: the 512-thread
+            // kernel (twice the waves per CU in flight); it loses on the
+            // smaller tiles (fewer words per thread than lanes can hide)
             const bool wide =
-                !quorum && pick_wide(c, P.s == kMaxSuffix);
+                !quorum && pick_wide(c, P.s >= kWideMinSuffix);
             const int tgrid =
                 grid_for(c, wide ? c->tiled_wide_bpc : c->tiled_bpc);
             // sibling tiles share one string order: items of kOrderReuse

@@ -117,11 +117,11 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         double total_cost = 0, wide_cost = 0;
         for (auto &b : mem) {
             total_cost += b.cost;
-            if (b.s == kMaxSuffix)
+            if (b.s >= kWideMinSuffix)
                 wide_cost += b.cost;
         }
         // the 512-thread tile kernel when most of the work is in tiles of
-        // 4^9 codes (it is faster there and about even elsewhere)
+        // at least 4^8 codes (faster there, slower on smaller tiles)
         const bool wide = pick_wide(c, wide_cost >= 0.5 * total_cost);
         const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
         const double slots = (double)std::max(1, c->n_cu * tbpc);

@@ -339,12 +339,12 @@ void Server::run()
             }
             took[a] = t - r->next_tile;
             planned += (double)took[a] * r->cost_per_tile;
-            if (r->s == kMaxSuffix)
+            if (r->s >= kWideMinSuffix)
                 planned_wide += (double)took[a] * r->cost_per_tile;
         }
         if (rc == PMS_OK && ni > 0) {
             // the 512-thread tile kernel when most of this launch's work is
-            // in tiles of 4^9 codes
+            // in tiles of at least 4^8 codes
             const bool wide = pick_wide(c, planned_wide >= 0.5 * planned);
             const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
             if (hipMemcpyAsync(d_items, h_items, sizeof(WorkItem) * ni,
