@@ -142,6 +142,8 @@ struct pms_ctx {
 
 namespace pms {
 
+constexpr int kWideMinSuffix = 8;  // 512-thread tile kernel from 4^8 codes
+
 inline bool pick_wide(const pms_ctx *c, bool automatic)
 {
     return c->opt.tile_threads == 512 ||

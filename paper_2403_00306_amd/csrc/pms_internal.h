@@ -16,7 +16,6 @@ constexpr int kMaxWords = 1 << (2 * (kMaxSuffix - 3));
 constexpr int kWordsPerThread = kMaxWords / kTPB;   // 16
 constexpr int kYChunk = 640;       // l-mers staged per marking round
 constexpr int kSurvMax = 256;      // survivor list of the filter stage
-constexpr int kWideMinSuffix = 8;  // 512-thread tile kernel from 4^8 codes
 constexpr int kDefaultSurv = 64;   // default threshold to enter it
 constexpr int kOrderMax = 64;      // per-tile string order for n up to this
 #ifndef PMS_ORDER_REUSE
