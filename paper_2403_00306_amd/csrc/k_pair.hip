@@ -69,31 +69,48 @@ __device__ __forceinline__ void scan_string(const PairJob &J, int i,
 {
     const c_u64 *row = (const c_u64 *)(const void *)(
         J.planes + (size_t)i * J.L);
-    bool hit[kPairPer];
+    // running minimum distance per candidate (two l-mers per v_min3); a
+    // dead candidate starts at 0 so that it never holds the wave back
+    uint32_t mind[kPairPer];
 #pragma unroll
     for (int u = 0; u < kPairPer; u++) {
-        hit[u] = !live[u];
+        mind[u] = live[u] ? 255u : 0u;
         hc += live[u] ? (unsigned long long)J.L : 0ull;
     }
-    for (int y0 = 0; y0 < J.L; y0 += 8) {
-        const int y1 = min(y0 + 8, J.L);
-        for (int yy = y0; yy < y1; yy++) {
-            const unsigned long long v = row[yy];
-            const uint32_t vh = (uint32_t)v, vl = (uint32_t)(v >> 32);
+    const uint32_t dd = (uint32_t)J.d;
+    int y0 = 0;
+    for (; y0 + 8 <= J.L; y0 += 8) {
+#pragma unroll
+        for (int yy = 0; yy < 8; yy += 2) {
+            const unsigned long long v0 = row[y0 + yy], v1 = row[y0 + yy + 1];
+            const uint32_t h0 = (uint32_t)v0, l0 = (uint32_t)(v0 >> 32);
+            const uint32_t h1 = (uint32_t)v1, l1 = (uint32_t)(v1 >> 32);
 #pragma unroll
             for (int u = 0; u < kPairPer; u++)
-                hit[u] |= __popc((ch[u] ^ vh) | (cl[u] ^ vl)) <= J.d;
+                mind[u] = min(mind[u],
+                              min((uint32_t)__popc((ch[u] ^ h0) | (cl[u] ^ l0)),
+                                  (uint32_t)__popc((ch[u] ^ h1) | (cl[u] ^ l1))));
         }
         bool done = true;
 #pragma unroll
         for (int u = 0; u < kPairPer; u++)
-            done &= hit[u];
+            done &= mind[u] <= dd;
         if (__all(done))
             break;
     }
+    if (y0 + 8 > J.L) {
+        for (int yy = y0; yy < J.L; yy++) {
+            const unsigned long long v = row[yy];
+            const uint32_t vh = (uint32_t)v, vl = (uint32_t)(v >> 32);
+#pragma unroll
+            for (int u = 0; u < kPairPer; u++)
+                mind[u] = min(mind[u],
+                              (uint32_t)__popc((ch[u] ^ vh) | (cl[u] ^ vl)));
+        }
+    }
 #pragma unroll
     for (int u = 0; u < kPairPer; u++)
-        live[u] &= hit[u];
+        live[u] &= mind[u] <= dd;
 }
 
 // Append the lanes' kept entries with one atomic per wave (lanes that are
