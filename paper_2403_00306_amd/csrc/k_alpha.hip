@@ -57,6 +57,22 @@ k_alpha_index(const uint8_t *seqs, const uint8_t *map, int n, int m, int l,
 
 typedef __attribute__((address_space(4))) const uint32_t c_u32;
 
+// Hamming distance between a candidate and an l-mer over 5 bit planes:
+// popcount(OR_b (c_b XOR a_b)). v_bitop3 with truth table 0xF6 computes
+// s0 | (s1 ^ s2) (table index s0*4 + s1*2 + s2), one instruction per plane
+// after the first.
+__device__ __forceinline__ uint32_t dist5(const uint32_t *c, uint32_t a0,
+                                          uint32_t a1, uint32_t a2,
+                                          uint32_t a3, uint32_t a4)
+{
+    uint32_t t = c[0] ^ a0;
+    t = __builtin_amdgcn_bitop3_b32(t, c[1], a1, 0xF6);
+    t = __builtin_amdgcn_bitop3_b32(t, c[2], a2, 0xF6);
+    t = __builtin_amdgcn_bitop3_b32(t, c[3], a3, 0xF6);
+    t = __builtin_amdgcn_bitop3_b32(t, c[4], a4, 0xF6);
+    return (uint32_t)__popc(t);
+}
+
 __global__ __launch_bounds__(kTPB) void
 k_alpha_filter(AlphaJob J, unsigned int *next, unsigned long long nitems)
 {
@@ -124,36 +140,52 @@ k_alpha_filter(AlphaJob J, unsigned int *next, unsigned long long nitems)
                 break;
             const c_u32 *row = (const c_u32 *)(const void *)(
                 J.planes + (size_t)i * J.L * kAlphaStride);
-            bool hit[kAlphaPer];
+            // running minimum distance per candidate; a dead candidate
+            // starts at 0 so that it never holds the wave back
+            uint32_t mind[kAlphaPer];
 #pragma unroll
             for (int u = 0; u < kAlphaPer; u++) {
-                hit[u] = !live[u];
+                mind[u] = live[u] ? 255u : 0u;
                 hc += live[u] ? (unsigned long long)J.L : 0ull;
             }
-            for (int y0 = 0; y0 < J.L; y0 += 8) {
-                const int y1 = min(y0 + 8, J.L);
-                for (int y = y0; y < y1; y++) {
-                    const c_u32 *yp = row + (size_t)y * kAlphaStride;
+            const uint32_t dd = (uint32_t)J.d;
+            int y0 = 0;
+            for (; y0 + 8 <= J.L; y0 += 8) {
+#pragma unroll
+                for (int y = 0; y < 8; y += 2) {
+                    const c_u32 *yp = row + (size_t)(y0 + y) * kAlphaStride;
+                    const c_u32 *zp = yp + kAlphaStride;
                     const uint32_t a0 = yp[0], a1 = yp[1], a2 = yp[2],
                                    a3 = yp[3], a4 = yp[4];
+                    const uint32_t b0 = zp[0], b1 = zp[1], b2 = zp[2],
+                                   b3 = zp[3], b4 = zp[4];
 #pragma unroll
-                    for (int u = 0; u < kAlphaPer; u++) {
-                        const uint32_t x = (cp[u][0] ^ a0) | (cp[u][1] ^ a1) |
-                                           (cp[u][2] ^ a2) | (cp[u][3] ^ a3) |
-                                           (cp[u][4] ^ a4);
-                        hit[u] |= __popc(x) <= J.d;
-                    }
+                    for (int u = 0; u < kAlphaPer; u++)
+                        mind[u] = min(mind[u],
+                                      min(dist5(cp[u], a0, a1, a2, a3, a4),
+                                          dist5(cp[u], b0, b1, b2, b3, b4)));
                 }
                 bool done = true;
 #pragma unroll
                 for (int u = 0; u < kAlphaPer; u++)
-                    done &= hit[u];
+                    done &= mind[u] <= dd;
                 if (__all(done))
                     break;
             }
+            if (y0 + 8 > J.L) {
+                for (int y = y0; y < J.L; y++) {
+                    const c_u32 *yp = row + (size_t)y * kAlphaStride;
+                    const uint32_t a0 = yp[0], a1 = yp[1], a2 = yp[2],
+                                   a3 = yp[3], a4 = yp[4];
+#pragma unroll
+                    for (int u = 0; u < kAlphaPer; u++)
+                        mind[u] = min(mind[u],
+                                      dist5(cp[u], a0, a1, a2, a3, a4));
+                }
+            }
 #pragma unroll
             for (int u = 0; u < kAlphaPer; u++)
-                live[u] &= hit[u];
+                live[u] &= mind[u] <= dd;
         }
         // survivors: base-sigma code, first letter in the top digit
 #pragma unroll
