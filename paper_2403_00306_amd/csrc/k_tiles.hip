@@ -742,14 +742,18 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
     __syncthreads();   // the previous tile may still be reading sh.U
 
+    // Every counter starts at 2^kQPlanes - 1 - T: a code is still live
+    // after T misses and its (T+1)-th miss carries out of the top plane,
+    // which is the test itself (no compare with T per pass).
     unsigned long long C[kQPlanes][kQWords];
     unsigned long long live[kQWords];
+    const uint32_t c0 = (uint32_t)((1 << kQPlanes) - 1 - T);
 #pragma unroll
     for (int k = 0; k < kQWords; k++) {
         live[k] = (tid + k * kTPB < W) ? ~0ull : 0ull;
 #pragma unroll
         for (int p = 0; p < kQPlanes; p++)
-            C[p][k] = 0;
+            C[p][k] = ((c0 >> p) & 1u) ? ~0ull : 0ull;
     }
     bool any = true;
     for (int si = 0; si < I.n; si++) {
@@ -776,18 +780,8 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
                     C[p][k] ^= carry;
                     carry = c2;
                 }
-                // count > T, compared from the top bit down
-                unsigned long long gt = 0, eq = ~0ull;
-#pragma unroll
-                for (int p = kQPlanes - 1; p >= 0; p--) {
-                    if ((T >> p) & 1) {
-                        eq &= C[p][k];
-                    } else {
-                        gt |= eq & C[p][k];
-                        eq &= ~C[p][k];
-                    }
-                }
-                live[k] &= ~gt;
+                // a carry out of the top plane is the (T+1)-th miss
+                live[k] &= ~carry;
                 nz |= live[k] != 0;
             }
         }
