@@ -117,12 +117,12 @@ InstDev make_desc(char *base, const InstLayout &o, const uint8_t *seqs,
     I.wpr = (m + 31) / 32;
     I.q = n;
     // per-tile string order (tiled path): worth its n*L prefix tests per
-    // tile where a pass's expected word marks, L * n_B(l-3, d) / 4^(l-s),
-    // are well above them
+    // tile (shared by sibling tiles) where a pass's expected word marks,
+    // L * n_B(l-3, d) / 4^(l-s), are above half of them
     if (n <= kOrderMax && s >= 3 && l >= s) {
         const double L = (double)(m - l + 1);
         const double marks = L * nb_real(l - 3, d) / std::pow(4.0, l - s);
-        I.tile_order = marks >= 1.5 * (double)n * L ? 1 : 0;
+        I.tile_order = marks >= 0.5 * (double)n * L ? 1 : 0;
     } else {
         I.tile_order = 0;
     }
