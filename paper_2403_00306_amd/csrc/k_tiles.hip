@@ -903,8 +903,8 @@ k_tiled_512(const InstDev *insts, const WorkItem *items, int nitems,
                                  stats);
 }
 
-// 256 threads: at 512 the bit-sliced counters no longer fit 64 VGPRs
-// without spills in the pass loop (measured 1.5x slower)
+// 256 threads: at 512 the bit-sliced counters spill at 64 VGPRs; with the
+// preloaded counters that costs about what the extra waves gain
 constexpr int kQuorumTPB = kTPB;
 
 __global__ __launch_bounds__(kQuorumTPB, kQuorumTPB / 64) void
