@@ -280,6 +280,38 @@ def test_tile_order_and_long_strings():
             np.testing.assert_array_equal(got, want, err_msg="t=%d" % t)
 
 
+def mutated_copies(seed, n, m, k, muts):
+    # n strings, each a copy of one of k random strings with `muts` random
+    # positions redrawn: dense motif sets in which every string differs
+    rng = random.Random(seed)
+    pool = [bytearray(rng.choice(ACGT) for _ in range(m)) for _ in range(k)]
+    out = bytearray()
+    for i in range(n):
+        s = bytearray(pool[i % k])
+        for _ in range(muts):
+            s[rng.randrange(m)] = rng.choice(ACGT)
+        out += s
+    return bytes(out)
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_string_order_limit_vs_oracle(threads):
+    # (16,6) at s = 9: 4^7 tiles, enough for items of four sibling tiles that
+    # share one string order (with 4 workgroups per CU); n = 64 is the
+    # largest n the per-tile order covers, n = 65 runs in input order
+    n_l, n_d, m = 16, 6, 30
+    for n in (64, 65):
+        seqs = mutated_copies(64 + n, n, m, 2, 1)
+        want = oracle_set(seqs, n, m, n_l, n_d)
+        assert len(want) > 10000
+        with pms.Context(path=pms.PATH_TILED, tile_threads=threads) as c:
+            c.set_tile_config(n_l, n_d, 9, 64)
+            say("order limit n", n, "threads", threads)
+            got = c.solve(seqs, n, m, n_l, n_d)
+            assert c.stats()["tile_threads"] == threads
+        np.testing.assert_array_equal(got, want, err_msg="n=%d" % n)
+
+
 def test_repeat_runs_identical(ctx):
     inst = pmsgen.plain("pms_13_4", 4)
     a = ctx.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d)
