@@ -274,10 +274,12 @@ typedef struct {
     uint64_t retries;         /* output-capacity retries */
     uint64_t pairs;           /* pair path: pairs (x, y) with d_H <= 2d */
     uint64_t candidates;      /* pair path: sum of |B(x,d) ∩ B(y,d)| */
-    int tile_threads;         /* tiled path (single instance): threads per
-                                 workgroup of the tile kernel, 512 for
-                                 tiles of 4^8 or 4^9 codes, else 256; 0
-                                 otherwise */
+    int tile_threads;         /* tiled path: threads per workgroup of the
+                                 tile kernel (256 or 512; unless forced by
+                                 pms_options.tile_threads: 512 for tiles of
+                                 4^8 or 4^9 codes, and for a batch when
+                                 most of its planned work is in such
+                                 tiles); 0 when no tile kernel ran */
 } pms_stats;
 
 int pms_last_stats(const pms_ctx *ctx, pms_stats *out);

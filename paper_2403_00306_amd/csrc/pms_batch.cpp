@@ -383,6 +383,7 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         S.tile_passes = ts.passes;
         S.marks = ts.marks;
         S.filter_tests = ts.ftests;
+        S.tile_threads = wide ? 512 : 256;
         break;
     }
     // instances the tiled kernel does not suit run one by one

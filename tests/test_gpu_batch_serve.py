@@ -45,6 +45,25 @@ def test_batch_matches_oracle_and_alone():
         np.testing.assert_array_equal(alone[i], want)
 
 
+@pytest.mark.parametrize("threads", [0, 256, 512])
+def test_batch_tile_kernel_sizes(threads):
+    # (13,4) and (14,4) take tiles of 4^8 and 4^9 codes, where the automatic
+    # choice is the 512-thread kernel; forced sizes run every tile with it
+    insts = mixed_instances(33, 10, [(9, 2), (13, 4), (14, 4)], (4, 8),
+                            (60, 120))
+    say("batch threads", threads)
+    with pms.Context(tile_threads=threads) as c:
+        got = c.solve_batch(insts)
+        st = c.stats()
+        alone = [c.solve(x.seqs, x.n, x.m, x.l, x.d) for x in insts]
+    if st["tiles"] > 0:
+        assert st["tile_threads"] == (threads or 512)
+    for i, x in enumerate(insts):
+        want = oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0]
+        np.testing.assert_array_equal(got[i], want, err_msg="inst %d" % i)
+        np.testing.assert_array_equal(alone[i], want, err_msg="inst %d" % i)
+
+
 def test_batch_bad_instance_does_not_spoil_others():
     insts = mixed_instances(5, 6, [(9, 2), (10, 2)], (4, 8), (50, 120))
     bad = bytearray(insts[2].seqs)
