@@ -97,6 +97,23 @@ def test_batch_large_output_retry():
     assert st["retries"] >= 1
 
 
+@pytest.mark.parametrize("threads", [256, 512])
+def test_served_tile_kernel_sizes(threads):
+    # every serving launch on one forced workgroup size of the tile kernel
+    reqs = mixed_instances(41, 12, [(9, 2), (13, 4)], (4, 8), (60, 150))
+    say("served threads", threads)
+    with pms.Context(serve_slots=4, tile_threads=threads) as c:
+        tickets = [c.submit(x.seqs, x.n, x.m, x.l, x.d) for x in reqs]
+        res = [c.wait(t, 60000) for t in tickets]
+        for t in tickets:
+            c.release(t)
+    for i, x in enumerate(reqs):
+        assert res[i] is not None
+        np.testing.assert_array_equal(
+            res[i], oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0],
+            err_msg="request %d" % i)
+
+
 def test_served_requests_match_alone_and_oracle():
     reqs = mixed_instances(33, 40, [(9, 2), (11, 3), (13, 4), (8, 1)],
                            (5, 20), (100, 600))
