@@ -312,6 +312,23 @@ def test_string_order_limit_vs_oracle(threads):
         np.testing.assert_array_equal(got, want, err_msg="n=%d" % n)
 
 
+def test_tile_count_limit():
+    # l = 23 at s = 9 is exactly 4^14 tiles, the most the tiled path takes;
+    # at l = 24 a forced tiled solve runs on the filter path instead
+    for l in (23, 24):
+        seqs = mutated_copies(100 + l, 3, 30, 1, 1)
+        want = oracle_set(seqs, 3, 30, l, 3)
+        assert len(want) > 10000
+        say("tile limit l", l)
+        got, st = solve_path(pms.PATH_TILED, seqs, 3, 30, l, 3)
+        np.testing.assert_array_equal(got, want, err_msg="l=%d" % l)
+        if l == 23:
+            assert st["path"] == pms.PATH_TILED
+            assert st["tile_suffix"] == 9 and st["tiles"] == 4 ** 14
+        else:
+            assert st["path"] == pms.PATH_FILTER
+
+
 def test_repeat_runs_identical(ctx):
     inst = pmsgen.plain("pms_13_4", 4)
     a = ctx.solve(inst.seqs, inst.n, inst.m, inst.l, inst.d)
