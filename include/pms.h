@@ -167,7 +167,8 @@ int pms_solve_quorum_device(pms_ctx *ctx, const uint8_t *d_seqs, int n,
  * from the spheres of s_1's l-mers, strings tested in order with early
  * exit), then sorts and drops repeats on the device. Output as pms_solve.
  * PMS_EBASE for a byte outside the alphabet; PMS_EINVAL for a bad shape, a
- * bad alphabet, sigma^l beyond 64 bits or a sphere beyond 2^62 candidates
+ * bad alphabet, sigma^l above 2^64 (codes past 64 bits; 2^64 itself, as
+ * 16^16, is allowed) or a sphere beyond 2^62 candidates
  * (or 2^22 position sets). alphabet "ACGT" with sigma 4 is pms_solve.
  */
 int pms_solve_alphabet(pms_ctx *ctx, const char *alphabet, int sigma,

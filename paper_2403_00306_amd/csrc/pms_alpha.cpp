@@ -16,15 +16,17 @@ using namespace pms;
 namespace {
 
 // sigma^l, or 0 if it does not fit in 64 bits
-uint64_t space_of(int sigma, int l)
+// sigma^l, the size of the code space, exact up to 2^64 (past that only
+// known to be above it). Codes 0 .. sigma^l - 1 fit in 64 bits iff
+// sigma^l <= 2^64.
+constexpr unsigned __int128 kSpace64 = ((unsigned __int128)1) << 64;
+
+unsigned __int128 space_of(int sigma, int l)
 {
     unsigned __int128 v = 1;
-    for (int j = 0; j < l; j++) {
+    for (int j = 0; j < l && v <= kSpace64; j++)
         v *= (unsigned)sigma;
-        if (v > (((unsigned __int128)1) << 64) - 1)
-            return 0;
-    }
-    return (uint64_t)v;
+    return v;
 }
 
 struct AlphaPlan {
@@ -77,13 +79,10 @@ bool plan_alpha(int sigma, int l, int d, AlphaPlan &P)
     P.cum[d + 1] = (uint64_t)acc;
     P.posoff[d + 1] = P.posset.size();
     P.nb = (uint64_t)acc;
-    const uint64_t space = space_of(sigma, l);
-    int bits = 64;
-    if (space) {
-        bits = 0;
-        while (bits < 64 && (1ull << bits) < space)
-            bits++;
-    }
+    const unsigned __int128 space = space_of(sigma, l);
+    int bits = 0;
+    while (bits < 64 && (((unsigned __int128)1) << bits) < space)
+        bits++;
     P.key_bits = std::max(bits, 1);
     return true;
 }
@@ -110,7 +109,7 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
             return c->fail(PMS_EINVAL, "alphabet: letter '%c' repeated", ch);
         map[ch] = (uint8_t)i;
     }
-    if (space_of(sigma, l) == 0)
+    if (space_of(sigma, l) > kSpace64)
         return c->fail(PMS_EINVAL, "alphabet: %d^%d codes do not fit in 64 "
                        "bits", sigma, l);
     AlphaPlan P;

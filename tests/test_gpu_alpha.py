@@ -53,6 +53,32 @@ def test_alpha_random_small(ctx, sigma):
             (sigma, n, m, l, d)
 
 
+def test_alpha_top_of_code_range(ctx):
+    # the largest l whose codes fit in 64 bits for each alphabet size: at
+    # 4^32 = 16^16 = 2^64 and 9^20 > 2^63 many motif codes have the top bit
+    # set (the device sort must order them as unsigned); 20^14 is the protein
+    # limit. l + 1 is rejected. Dense sets from near-copies of one string.
+    rng = random.Random(71)
+    for alphabet, l, m in [(b"ACGT", 32, 40), (LETTERS[:16], 16, 30),
+                           (LETTERS[:9], 20, 30), (pmsgen.PROTEIN, 14, 30)]:
+        base = bytearray(rng.choice(alphabet) for _ in range(m))
+        seqs = bytearray()
+        for _ in range(3):
+            s = bytearray(base)
+            s[rng.randrange(m)] = rng.choice(alphabet)
+            seqs += s
+        seqs = bytes(seqs)
+        say("code range", len(alphabet), l)
+        want = oracle.s1(seqs, alphabet, 3, m, l, 2)
+        got = ctx.solve_alphabet(alphabet, seqs, 3, m, l, 2)
+        assert got.shape == want.shape and (got == want).all(), \
+            (len(alphabet), l)
+        if len(alphabet) != 20:
+            assert (want >= np.uint64(1 << 63)).any()
+        with pytest.raises(pms.PmsError):
+            ctx.solve_alphabet(alphabet, seqs, 3, m, l + 1, 2)
+
+
 def test_alpha_repeats(ctx):
     # low-complexity strings: each motif lies in the spheres of many l-mers
     alphabet = pmsgen.PROTEIN
