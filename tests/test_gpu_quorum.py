@@ -129,6 +129,28 @@ def test_quorum_edges(ctx):
         ctx.solve_quorum(bytes(bad), inst.n, inst.m, 9, 2, 10)
 
 
+def test_quorum_largest_l(ctx):
+    # l = 22 with tiles of 4^8 codes is 4^14 tiles, the most the quorum path
+    # takes (l = 23 is rejected above); strings are near-copies of two random
+    # strings (one base redrawn each), so the sets are dense
+    rng = random.Random(22)
+    pool = [bytes(rng.choice(ACGT) for _ in range(30)) for _ in range(2)]
+    for n, q in [(4, 2), (5, 3)]:
+        seqs = bytearray()
+        for i in range(n):
+            s = bytearray(pool[i % 2])
+            s[rng.randrange(30)] = rng.choice(ACGT)
+            seqs += s
+        seqs = bytes(seqs)
+        want = oracle.q1(seqs, n, 30, 22, 3, q)
+        assert len(want) > 10000
+        say("quorum l=22 n", n, "q", q)
+        got = ctx.solve_quorum(seqs, n, 30, 22, 3, q)
+        assert got.shape == want.shape and (got == want).all(), (n, q)
+        st = ctx.stats()
+        assert st["tile_suffix"] == 8 and st["tiles"] == 4 ** 14
+
+
 def test_quorum_order_invariance(ctx):
     inst = pmsgen.plain("pms_9_2", 2)
     rows = [inst.seqs[i * inst.m:(i + 1) * inst.m] for i in range(inst.n)]
