@@ -88,6 +88,30 @@ def test_pair_17_6_equals_tiled(pctx):
     assert st["candidates"] < 584 * oracle.nb(17, 6)
 
 
+def test_pair_long_motifs(pctx):
+    # l up to 32 (a full 32-bit word per bit plane), planted and on
+    # near-copies of one random string (one base redrawn per string), whose
+    # sets are dense
+    for (n, m, l, d) in [(4, 60, 32, 2), (5, 80, 20, 3), (3, 50, 25, 1)]:
+        rng = random.Random(l + d)
+        base = bytes(rng.choice(ACGT) for _ in range(m))
+        near = bytearray()
+        for _ in range(n):
+            s = bytearray(base)
+            s[rng.randrange(m)] = rng.choice(ACGT)
+            near += s
+        for kind, seqs in (("planted", pmsgen.planted(l * 7 + d, n, m, l,
+                                                       d).seqs),
+                           ("near-copies", bytes(near))):
+            say("pair long", kind, (n, m, l, d))
+            got = pctx.solve(seqs, n, m, l, d)
+            want, _ = oracle.o1(seqs, n, m, l, d)
+            assert got.shape == want.shape and (got == want).all(), \
+                (kind, l, d)
+            _, nc = oracle.p1(seqs, n, m, l, d)
+            assert pctx.stats()["candidates"] == nc
+
+
 def test_pair_repeats(pctx):
     # every pair compatible, every motif reached from many pairs
     rows = [b"A" * 24, b"A" * 12 + b"C" * 12, b"A" * 24]
