@@ -312,6 +312,25 @@ def test_string_order_limit_vs_oracle(threads):
         np.testing.assert_array_equal(got, want, err_msg="n=%d" % n)
 
 
+def test_many_strings_every_path():
+    # hundreds of strings (n has no upper limit): near-copies of one random
+    # string, one base redrawn in each; every exact path, and the quorum at
+    # its largest miss budget n - q = 30
+    for (n, m, l, d) in [(300, 25, 9, 2), (1000, 20, 8, 2)]:
+        seqs = mutated_copies(n, n, m, 1, 1)
+        want = oracle_set(seqs, n, m, l, d)
+        assert len(want) > 100
+        for path in PATHS + [pms.PATH_PAIR]:
+            say("many strings n", n, "path", path)
+            got, _ = solve_path(path, seqs, n, m, l, d)
+            np.testing.assert_array_equal(got, want,
+                                          err_msg="n=%d path=%d" % (n, path))
+        wq = oracle.q1(seqs, n, m, l, d, n - 30)
+        with pms.Context() as c:
+            gq = c.solve_quorum(seqs, n, m, l, d, n - 30)
+        np.testing.assert_array_equal(gq, wq, err_msg="quorum n=%d" % n)
+
+
 def test_tile_count_limit():
     # l = 23 at s = 9 is exactly 4^14 tiles, the most the tiled path takes;
     # at l = 24 a forced tiled solve runs on the filter path instead
