@@ -374,6 +374,19 @@ def test_solve_device_with_torch_buffers(ctx):
         ctx.solve_device(d_seqs.data_ptr(), inst.n, inst.m, inst.l, inst.d,
                          small.data_ptr(), 2)
     assert e.value.status == pms.PMS_ENOMEM and e.value.needed == len(want)
+    # capacity exactly the size of the set
+    exact = torch.zeros(len(want), dtype=torch.int64, device=dev)
+    cnt = ctx.solve_device(d_seqs.data_ptr(), inst.n, inst.m, inst.l, inst.d,
+                           exact.data_ptr(), len(want))
+    assert cnt == len(want)
+    np.testing.assert_array_equal(exact.cpu().numpy().view(np.uint64), want)
+    # an instance without motifs: count 0, with capacity 0
+    rng = random.Random(1)
+    none = bytes(rng.choice(ACGT) for _ in range(5 * 20))
+    assert len(oracle_set(none, 5, 20, 8, 1)) == 0
+    d_none = torch.frombuffer(bytearray(none), dtype=torch.uint8).to(dev)
+    assert ctx.solve_device(d_none.data_ptr(), 5, 20, 8, 1,
+                            exact.data_ptr(), 0) == 0
 
 
 def test_error_paths(ctx):
