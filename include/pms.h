@@ -281,6 +281,10 @@ typedef struct {
                                  4^8 or 4^9 codes, and for a batch when
                                  most of its planned work is in such
                                  tiles); 0 when no tile kernel ran */
+    int graph_replayed;       /* pms_solve_batch: 1 when the call replayed
+                                 the HIP graph captured by an earlier call
+                                 of the same batch shape, 0 when it
+                                 captured one; 0 for other calls */
 } pms_stats;
 
 int pms_last_stats(const pms_ctx *ctx, pms_stats *out);

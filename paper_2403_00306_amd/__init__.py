@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("filter_tests", ctypes.c_uint64),
                 ("bytes_main", ctypes.c_uint64), ("retries", ctypes.c_uint64),
                 ("pairs", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
-                ("tile_threads", ctypes.c_int)]
+                ("tile_threads", ctypes.c_int),
+                ("graph_replayed", ctypes.c_int)]
 
 
 class ServeStats(ctypes.Structure):

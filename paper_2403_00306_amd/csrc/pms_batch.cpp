@@ -241,7 +241,8 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         HIPCHK(c, hipEventRecord(c->ev[0], st));
         HIPCHK(c, hipMemcpyAsync(base, P, seq_bytes, hipMemcpyHostToDevice,
                                  st));
-        if (key != c->b_graph_key || !c->b_graph) {
+        const bool replay = key == c->b_graph_key && c->b_graph;
+        if (!replay) {
             if (c->b_graph) {
                 hipGraphExecDestroy(c->b_graph);
                 hipGraphDestroy(c->b_graph_def);
@@ -384,6 +385,7 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         S.marks = ts.marks;
         S.filter_tests = ts.ftests;
         S.tile_threads = wide ? 512 : 256;
+        S.graph_replayed = replay ? 1 : 0;
         break;
     }
     // instances the tiled kernel does not suit run one by one

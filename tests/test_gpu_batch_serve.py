@@ -45,6 +45,26 @@ def test_batch_matches_oracle_and_alone():
         np.testing.assert_array_equal(alone[i], want)
 
 
+def test_batch_graph_replays_with_eager_work_between():
+    # the first call captures the batch's graph, the next three replay it;
+    # a plain solve (other kernels, a host synchronisation) runs between
+    # replays, and every replay is checked against the oracle
+    insts = mixed_instances(57, 16, [(9, 2), (11, 3), (13, 4)], (4, 10),
+                            (50, 200))
+    want = [oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0] for x in insts]
+    with pms.Context() as c:
+        for rep in range(4):
+            got = c.solve_batch(insts)
+            assert c.stats()["graph_replayed"] == (1 if rep else 0), rep
+            for i in range(len(insts)):
+                np.testing.assert_array_equal(
+                    got[i], want[i], err_msg="replay %d inst %d" % (rep, i))
+            x = insts[rep]
+            np.testing.assert_array_equal(
+                c.solve(x.seqs, x.n, x.m, x.l, x.d), want[rep])
+            assert c.stats()["graph_replayed"] == 0
+
+
 @pytest.mark.parametrize("threads", [0, 256, 512])
 def test_batch_tile_kernel_sizes(threads):
     # (13,4) and (14,4) take tiles of 4^8 and 4^9 codes, where the automatic
