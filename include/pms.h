@@ -212,6 +212,9 @@ int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
  * it; the context's engine thread admits queued requests while device
  * memory and slots allow and runs admitted requests' work together, a
  * bounded slice per launch, so requests join and leave between launches.
+ * Each launch aims at about 8 ms of device time, shared equally by cost
+ * among the admitted requests (processor sharing): a small request finishes
+ * within a launch or two, a large one in proportion to its size and load.
  * *ticket identifies the request. PMS_EBUSY if the waiting queue is full;
  * PMS_EINVAL for a bad shape, for a shape the tiled path does not suit
  * (l < 3, or more than 4^14 tiles; use pms_solve) and PMS_ENOMEM for a
