@@ -94,6 +94,12 @@ typedef struct {
                                  kernel, 256 or 512; 0 = automatic (512
                                  where the tiles hold 4^8 or 4^9 codes).
                                  The result does not depend on it. */
+    double serve_launch_ms;   /* serving: device time each launch aims at,
+                                 in ms; 0 = 16. Shorter launches finish
+                                 small requests sooner; longer ones waste
+                                 less of the GPU on the host work between
+                                 launches (more capacity, lower p99). The
+                                 results do not depend on it. */
 } pms_options;
 
 /* Fill *opt with the defaults above (device 0, auto path). */
@@ -212,9 +218,10 @@ int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
  * it; the context's engine thread admits queued requests while device
  * memory and slots allow and runs admitted requests' work together, a
  * bounded slice per launch, so requests join and leave between launches.
- * Each launch aims at about 8 ms of device time, shared equally by cost
- * among the admitted requests (processor sharing): a small request finishes
- * within a launch or two, a large one in proportion to its size and load.
+ * Each launch aims at pms_options.serve_launch_ms of device time (default
+ * 16 ms), shared equally by cost among the admitted requests (processor
+ * sharing): a small request finishes within a launch or two, a large one in
+ * proportion to its size and load.
  * *ticket identifies the request. PMS_EBUSY if the waiting queue is full;
  * PMS_EINVAL for a bad shape, for a shape the tiled path does not suit
  * (l < 3, or more than 4^14 tiles; use pms_solve) and PMS_ENOMEM for a

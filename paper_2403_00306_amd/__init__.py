@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
                 ("mem_budget_bytes", ctypes.c_size_t),
                 ("tune_cache", ctypes.c_char_p),
                 ("serve_slots", ctypes.c_int), ("serve_queue", ctypes.c_int),
-                ("tile_threads", ctypes.c_int)]
+                ("tile_threads", ctypes.c_int),
+                ("serve_launch_ms", ctypes.c_double)]
 
 
 class CInstance(ctypes.Structure):
@@ -168,7 +169,7 @@ class Context:
     def __init__(self, device: int = 0, path: int = PATH_AUTO,
                  mem_budget_bytes: int = 0, tune_cache: str | None = None,
                  serve_slots: int = 0, serve_queue: int = 0,
-                 tile_threads: int = 0):
+                 tile_threads: int = 0, serve_launch_ms: float = 0.0):
         self._lib = load_library()
         opt = Options()
         self._lib.pms_default_options(ctypes.byref(opt))
@@ -179,6 +180,7 @@ class Context:
         opt.serve_slots = serve_slots
         opt.serve_queue = serve_queue
         opt.tile_threads = tile_threads
+        opt.serve_launch_ms = serve_launch_ms
         h = ctypes.c_void_p()
         rc = self._lib.pms_create(ctypes.byref(h), ctypes.byref(opt))
         if rc != PMS_OK:

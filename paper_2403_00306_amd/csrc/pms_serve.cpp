@@ -27,10 +27,10 @@ namespace pms {
 
 namespace {
 
-// device time aimed at per launch: every launch ends in a host
+// default device time aimed at per launch: every launch ends in a host
 // synchronisation, so longer launches waste less of the GPU between them
 // (at the cost of a longer wait for the smallest requests)
-constexpr double kLaunchTargetMs = 8.0;
+constexpr double kLaunchTargetMs = 16.0;
 constexpr int kMaxOrder = 4096;          // strings per request (serving)
 
 // First-fit sub-allocator over one device allocation (host bookkeeping).
@@ -111,6 +111,7 @@ struct Server {
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
     int max_slots = 64, max_queue = 4096;
+    double launch_ms = kLaunchTargetMs;   // device time aimed at per launch
     std::vector<int> free_slots;
     Pool pool;
     void *pool_mem = nullptr;
@@ -142,6 +143,8 @@ int Server::start()
     hipSetDevice(c->device);
     max_slots = c->opt.serve_slots ? c->opt.serve_slots : 64;
     max_queue = c->opt.serve_queue ? c->opt.serve_queue : 4096;
+    launch_ms = c->opt.serve_launch_ms > 0.0 ? c->opt.serve_launch_ms
+                                             : kLaunchTargetMs;
     size_t room = c->budget > c->held.load() ? c->budget - c->held.load() : 0;
     pool_bytes = std::min<size_t>(room / 2, (size_t)8 << 30);
     if (pool_bytes < ((size_t)64 << 20))
@@ -315,7 +318,7 @@ void Server::run()
 
         // ---- one launch: a slice of every admitted request's tiles ------
         const double t0 = now_ms();
-        const double budget = kLaunchTargetMs * ops_per_ms;
+        const double budget = launch_ms * ops_per_ms;
         const double share = budget / (double)act.size();
         size_t ni = 0;
         double planned = 0, planned_wide = 0;

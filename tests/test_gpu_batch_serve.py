@@ -134,6 +134,27 @@ def test_served_tile_kernel_sizes(threads):
             err_msg="request %d" % i)
 
 
+def test_served_launch_size():
+    # the launch size changes how requests share launches, never a result
+    reqs = mixed_instances(43, 12, [(9, 2), (11, 3), (13, 4)], (4, 8),
+                           (60, 150))
+    want = [oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0] for x in reqs]
+    for ms in (0.5, 32.0):
+        say("served launch ms", ms)
+        with pms.Context(serve_slots=4, serve_launch_ms=ms) as c:
+            tickets = [c.submit(x.seqs, x.n, x.m, x.l, x.d) for x in reqs]
+            res = [c.wait(t, 60000) for t in tickets]
+            for t in tickets:
+                c.release(t)
+        for i in range(len(reqs)):
+            assert res[i] is not None
+            np.testing.assert_array_equal(res[i], want[i],
+                                          err_msg="ms=%g request %d" % (ms, i))
+    for bad in (-1.0, float("nan"), 5000.0):
+        with pytest.raises(pms.PmsError):
+            pms.Context(serve_launch_ms=bad)
+
+
 def test_served_requests_match_alone_and_oracle():
     reqs = mixed_instances(33, 40, [(9, 2), (11, 3), (13, 4), (8, 1)],
                            (5, 20), (100, 600))
