@@ -3,7 +3,9 @@
 Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
 on inputs from the seeded generator; nothing here touches the GPU library.
 Run from the repository root:  python tests/golden/make_golden.py
-(add "quorum" or "protein" to write only those files)
+(add "quorum" or "protein" to write only those files; "large", "batched",
+"served" or "hard" write the long-running sets below, which take hours of
+CPU time and resume where an interrupted run stopped)
 """
 import hashlib
 import os
@@ -100,7 +102,187 @@ def main_protein():
         print("protein", seed, l, d, len(got), "%.1fs" % (time.time() - t0))
 
 
+# ---------------------------------------------------------------------------
+# Long runs: the (17,6) configuration, more seeds of the small ones, the
+# 256-instance batch, a sample of the served stream and sampled reference
+# l-mers of the harder instances. Every set comes from O1 alone (O0 is out of
+# reach above l = 13); at (9,2) and (13,4) O0 must agree as above.
+# ---------------------------------------------------------------------------
+
+THREADS = int(os.environ.get("GOLDEN_THREADS", "0"))   # 0 = every core
+# (17,6) seeds 1..5; more seeds of (9,2) and (13,4)
+LARGE = [("pms_9_2", 4), ("pms_9_2", 5), ("pms_13_4", 2), ("pms_13_4", 3),
+         ("pms_13_4", 4), ("pms_13_4", 5), ("pms_17_6", 1), ("pms_17_6", 2),
+         ("pms_17_6", 3), ("pms_17_6", 4), ("pms_17_6", 5)]
+
+
+def main_large():
+    for name, seed in LARGE:
+        path = os.path.join(HERE, "%s_seed%d.txt" % (name, seed))
+        if os.path.exists(path):
+            continue
+        inst = pmsgen.plain(name, seed)
+        t0 = time.time()
+        o1, h = oracle.o1(inst.seqs, inst.n, inst.m, inst.l, inst.d,
+                          threads=THREADS)
+        t1 = time.time()
+        both = inst.l <= 13
+        if both:
+            o0 = oracle.o0(inst.seqs, inst.n, inst.m, inst.l, inst.d,
+                           threads=THREADS)
+            assert list(o1) == list(o0), (name, seed)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            f.write("# Exact (l,d)-motif set of one synthetic planted instance,\n")
+            f.write("# written by tests/golden/make_golden.py from the CPU oracle\n")
+            f.write("# (%s).\n" % ("sample-driven O1 and brute-force O0 agree"
+                                   if both else "sample-driven O1"))
+            f.write("config = %s\nseed = %d\n" % (name, seed))
+            f.write("n = %d\nm = %d\nl = %d\nd = %d\n"
+                    % (inst.n, inst.m, inst.l, inst.d))
+            f.write("input_sha256 = %s\n" % hashlib.sha256(inst.seqs).hexdigest())
+            f.write("planted = %s\n" % inst.motif.decode())
+            f.write("hcanon = %d\n" % h)
+            f.write("count = %d\n" % len(o1))
+            f.write("motifs = %s\n" % ",".join(str(int(v)) for v in o1))
+            f.write("motif_strings = %s\n" % ",".join(
+                oracle.decode_code(v, inst.l).decode() for v in o1))
+            f.write("oracle_seconds = %.1f\n" % (t1 - t0))
+        os.replace(tmp, path)
+        print(name, seed, len(o1), "h=%d O1 %.1fs" % (h, t1 - t0), flush=True)
+
+
+def codes_sha256(codes) -> str:
+    return hashlib.sha256(codes.astype("<u8").tobytes()).hexdigest()
+
+
+SET_HEADER = ("# index n m l d input_sha256 count hcanon codes_sha256 codes\n"
+              "# (codes: the ascending motif codes when there are at most 64,\n"
+              "# else '-'; codes_sha256 hashes all of them as little-endian\n"
+              "# uint64)\n")
+
+
+def _done_indices(path):
+    done = set()
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#") and "=" not in line:
+                done.add(int(line.split()[0]))
+    return done
+
+
+def _append_sets(path, header, items):
+    """items: (index, Instance); one line per instance, appended as each
+    finishes, so that an interrupted run resumes."""
+    done = _done_indices(path)
+    if not os.path.exists(path):
+        with open(path, "w") as f:
+            f.write(header)
+            f.write(SET_HEADER)
+    for idx, inst in items:
+        if idx in done:
+            continue
+        t0 = time.time()
+        got, h = oracle.o1(inst.seqs, inst.n, inst.m, inst.l, inst.d,
+                           threads=THREADS)
+        codes = ",".join(str(int(v)) for v in got) if len(got) <= 64 else "-"
+        with open(path, "a") as f:
+            f.write("%d %d %d %d %d %s %d %d %s %s\n" % (
+                idx, inst.n, inst.m, inst.l, inst.d,
+                hashlib.sha256(inst.seqs).hexdigest(), len(got), h,
+                codes_sha256(got), codes if codes else "none"))
+        print(os.path.basename(path), idx, (inst.l, inst.d, inst.n, inst.m),
+              len(got), "%.1fs" % (time.time() - t0), flush=True)
+
+
+def main_batched():
+    insts = pmsgen.batched(seed=7, count=256)
+    path = os.path.join(HERE, "batched_seed7.txt")
+    header = ("# Exact motif sets of the 256 instances of pmsgen.batched(seed=7),\n"
+              "# written by tests/golden/make_golden.py from the CPU oracle O1.\n"
+              "recipe = batched(seed=7, count=256)\n")
+    # cheapest first, so a partial file already covers most instances
+    order = sorted(range(len(insts)), key=lambda i: (insts[i].l, insts[i].m))
+    _append_sets(path, header, [(i, insts[i]) for i in order])
+
+
+# Served stream: every request with l <= 13, and a seeded sample of at least
+# 10% of the (15,5) and of the (17,6) requests.
+SERVED_SAMPLE_SEED = 1511
+SERVED_SAMPLE_FRAC = 0.10
+
+
+def served_selection(reqs):
+    import math
+    import random
+    sel = [r.index for r in reqs if r.inst.l <= 13]
+    for ld in ((15, 5), (17, 6)):
+        pool = [r.index for r in reqs if (r.inst.l, r.inst.d) == ld]
+        k = int(math.ceil(SERVED_SAMPLE_FRAC * len(pool)))
+        sel += random.Random(SERVED_SAMPLE_SEED + ld[0]).sample(pool, k)
+    return sorted(sel, key=lambda i: (reqs[i].inst.l, i))
+
+
+def main_served(upto_l=17):
+    reqs = pmsgen.served(seed=11, count=2000)
+    path = os.path.join(HERE, "served_seed11.txt")
+    header = ("# Exact motif sets of the requests of pmsgen.served(seed=11,\n"
+              "# count=2000) with l <= 13 and of a seeded 10%% sample of the\n"
+              "# (15,5) and (17,6) requests (random.Random(%d + l).sample),\n"
+              "# written by tests/golden/make_golden.py from the CPU oracle O1.\n"
+              "recipe = served(seed=11, count=2000)\n" % SERVED_SAMPLE_SEED)
+    sel = [i for i in served_selection(reqs) if reqs[i].inst.l <= upto_l]
+    _append_sets(path, header, [(i, reqs[i].inst) for i in sel])
+
+
+# Harder instances (Table 3.3's (19,7), (21,8), (23,9) at n = 20, m = 600,
+# seed 1): the motifs O1 derives from a few reference l-mers of s_1 (the
+# plant's offset and seeded others). Each is a subset of the whole set.
+HARD = [(19, 7, 3), (21, 8, 3), (23, 9, 1)]
+
+
+def main_hard():
+    import random
+    path = os.path.join(HERE, "hard_refs_seed1.txt")
+    done = set()
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                done.add((int(t[0]), int(t[1]), int(t[2])))
+    else:
+        with open(path, "w") as f:
+            f.write("# Motifs that the CPU oracle O1 derives from single reference\n"
+                    "# l-mers of s_1 (offset j) of pmsgen.planted(1, 20, 600, l, d):\n"
+                    "# each list is a subset of the instance's motif set.\n"
+                    "# Written by tests/golden/make_golden.py.\n"
+                    "# l d j input_sha256 hcanon_of_j count codes\n")
+    for l, d, k in HARD:
+        inst = pmsgen.planted(1, 20, 600, l, d)
+        L = 600 - l + 1
+        refs = [inst.positions[0]]
+        others = [j for j in range(L) if j != inst.positions[0]]
+        refs += random.Random(1000 + l).sample(others, k - 1)
+        for j in refs:
+            if (l, d, j) in done:
+                continue
+            t0 = time.time()
+            got, h = oracle.o1(inst.seqs, 20, 600, l, d, ref_begin=j,
+                               ref_end=j + 1, threads=THREADS)
+            with open(path, "a") as f:
+                f.write("%d %d %d %s %d %d %s\n" % (
+                    l, d, j, hashlib.sha256(inst.seqs).hexdigest(), h,
+                    len(got), ",".join(str(int(v)) for v in got) or "none"))
+            print("hard", l, d, j, len(got), "%.1fs" % (time.time() - t0),
+                  flush=True)
+
+
 if __name__ == "__main__":
+    mode = sys.argv[1] if len(sys.argv) > 1 else ""
+    if mode in ("large", "batched", "served", "hard"):
+        {"large": main_large, "batched": main_batched,
+         "served": main_served, "hard": main_hard}[mode]()
+        sys.exit(0)
     if len(sys.argv) > 1 and sys.argv[1] == "protein":
         main_protein()
         sys.exit(0)

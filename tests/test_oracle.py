@@ -355,6 +355,95 @@ def test_invariants_on_planted_instance():
     assert set(Rmore) <= set(R)
 
 
+def py_is_motif(rows, l, d, M):
+    """Definition 5 for one l-mer M, literally: every string has an l-mer
+    within distance d of M."""
+    return all(any(py_dh(M, s[j:j + l]) <= d for j in range(len(s) - l + 1))
+               for s in rows)
+
+
+def test_is_motif_every_code_tiny():
+    # the per-code check accepts exactly the codes of Definition 5, over the
+    # whole code space: members and non-members alike
+    rng = random.Random(21)
+    n_false = n_true = 0
+    for _ in range(25):
+        l = rng.randint(2, 5)
+        d = rng.randint(0, min(2, l - 1))
+        n = rng.randint(1, 4)
+        m = rng.randint(l, 12)
+        rows = rand_rows(rng, n, m)
+        buf = b"".join(rows)
+        for c in range(4 ** l):
+            want = py_is_motif(rows, l, d, oracle.decode_code(c, l))
+            assert oracle.is_motif(buf, n, m, l, d, c) == want, (rows, l, d, c)
+            n_true += want
+            n_false += not want
+    assert n_true > 200 and n_false > 2000
+
+
+def test_is_motif_rejects_distance_d_plus_1():
+    # a code within d of an l-mer in every string but one, where its nearest
+    # l-mer is at exactly d + 1, is not a motif; moving one base of that
+    # l-mer onto the code makes it one
+    l, d = 6, 2
+    M = b"ACGTAC"
+    near = b"ACGTTT"                      # distance 2 = d
+    far = b"GTGTTC"                       # distance 3 = d + 1
+    assert py_dh(M, near) == d and py_dh(M, far) == d + 1
+    rows = [b"CC" + near + b"CC", b"GG" + M + b"GG", b"AA" + far + b"AA"]
+    # no other window of the last string is within d (checked literally)
+    assert not py_is_motif(rows, l, d, M)
+    buf = b"".join(rows)
+    code = py_code(M)
+    assert oracle.is_motif(buf, 3, 10, l, d, code) is False
+    assert oracle.hit_count(buf, 3, 10, l, d, code) == 2
+    fixed = rows[:2] + [b"AA" + b"ACGTTC" + b"AA"]   # distance 1 now
+    assert py_is_motif(fixed, l, d, M)
+    assert oracle.is_motif(b"".join(fixed), 3, 10, l, d, code) is True
+
+
+def test_is_motif_last_string_and_last_offset():
+    # the only string without a neighbour is the last one; the only
+    # neighbour of another string sits at its last offset
+    l, d = 5, 1
+    M = b"GATTC"
+    rows = [b"TTTT" + M, b"CCCCCCCCC", b"AAAA" + b"GATTA"]
+    assert not py_is_motif(rows, l, d, M)
+    buf = b"".join(rows)
+    assert oracle.is_motif(buf, 3, 9, l, d, py_code(M)) is False
+    rows2 = [b"TTTT" + M, b"CCCC" + b"GCTTC", b"AAAA" + b"GATTA"]
+    assert py_is_motif(rows2, l, d, M)
+    assert oracle.is_motif(b"".join(rows2), 3, 9, l, d, py_code(M)) is True
+
+
+def test_is_motif_planted_members_and_non_members():
+    # full-size (9,2) instance: the check agrees with membership in the
+    # stored set (pinned above through O0) on members and on sampled
+    # non-members, and non-members miss at least one string
+    kv, motifs = load_golden("pms_9_2_seed1.txt")
+    inst = pmsgen.plain("pms_9_2", 1)
+    n, m, l, d = inst.n, inst.m, inst.l, inst.d
+    member = set(motifs)
+    for c in motifs:
+        assert oracle.is_motif(inst.seqs, n, m, l, d, c)
+    rng = random.Random(92)
+    rows = inst.rows()
+    sample = [rng.randrange(4 ** l) for _ in range(300)]
+    # codes one base away from a member are near misses
+    for c in motifs:
+        for p in range(l):
+            sample.append(c ^ (1 << (2 * p)))
+    for c in sample:
+        got = oracle.is_motif(inst.seqs, n, m, l, d, c)
+        assert got == (c in member), c
+        if not got:
+            assert oracle.hit_count(inst.seqs, n, m, l, d, c) < n
+    # a literal recheck of a few rejected near misses
+    for c in [x for x in sample[300:] if x not in member][:6]:
+        assert not py_is_motif(rows, l, d, oracle.decode_code(c, l))
+
+
 def test_planted_generator_rule():
     for seed in range(5):
         inst = pmsgen.planted(seed, 12, 80, 9, 3)
