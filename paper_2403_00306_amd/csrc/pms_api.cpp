@@ -727,7 +727,6 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                 S.bytes_main = ntiles * tb + (ts.passes - ntiles) * 2 * tb;
             }
         }
-        S.retries += attempt;
         S.ms_total = now_ms() - t0;
         c->last = S;
         c->last_L = L;
