@@ -141,6 +141,28 @@ int pms_solve_device(pms_ctx *ctx, const uint8_t *d_seqs, int n, int m,
                      size_t *count);
 
 /*
+ * pms_solve_device for callers that cannot allocate device memory (code
+ * being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid allocation): same arguments, layout, ownership, output and
+ * PMS_ENOMEM-with-*count contract as pms_solve_device, but the call makes
+ * no hipMalloc, hipFree or other allocation. Its device working memory is a
+ * fixed 64 MiB array that each device the library runs on holds until the
+ * process ends (looked up by pms_create). It always runs the tiled path,
+ * so l must be at least 3 and the tiles at most 4^14 (PMS_EINVAL
+ * otherwise); an instance whose index, tile arrays and output heap do not
+ * fit in the array is rejected with PMS_ENOMEM before any launch (at
+ * n = 20, m = 600 that admits up to l = 19, i.e. up to 4^10 tiles), and
+ * PMS_ENOMEM with *count = the motif count when the motifs overflow the
+ * heap. The array keeps the last call's contents; what must start at zero
+ * is cleared by the call itself. All calls on one device share the one
+ * array: calls that overlap in time on the same device (other threads,
+ * other contexts, other streams) race and give undefined results.
+ */
+int pms_solve_device_noalloc(pms_ctx *ctx, const uint8_t *d_seqs, int n,
+                             int m, int l, int d, void *stream,
+                             uint64_t *d_out, size_t cap, size_t *count);
+
+/*
  * Quorum motifs (Definition 5 and the qPMS definition, Sec. 1.2.5): every
  * l-mer M such that at least q of the n strings have an l-mer within
  * Hamming distance d of M. q = n is exactly pms_solve. Same arguments,

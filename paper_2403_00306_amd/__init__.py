@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "pms_solve": (i, [vp, ctypes.c_char_p, i, i, i, i,
                           P(P(ctypes.c_uint64)), P(sz)]),
         "pms_solve_device": (i, [vp, vp, i, i, i, i, vp, vp, sz, P(sz)]),
+        "pms_solve_device_noalloc": (i, [vp, vp, i, i, i, i, vp, vp, sz,
+                                         P(sz)]),
         "pms_solve_quorum": (i, [vp, ctypes.c_char_p, i, i, i, i, i,
                                  P(P(ctypes.c_uint64)), P(sz)]),
         "pms_solve_quorum_device": (i, [vp, vp, i, i, i, i, i, vp, vp, sz,
@@ -238,6 +240,23 @@ class Context:
                                         ctypes.c_void_p(d_out), cap,
                                         ctypes.byref(cnt))
         if rc == PMS_ENOMEM and cnt.value > cap:
+            err = PmsError(rc, self._lib.pms_last_error(self._h).decode())
+            err.needed = cnt.value
+            raise err
+        self._check(rc)
+        return cnt.value
+
+    def solve_device_noalloc(self, d_seqs: int, n: int, m: int, l: int,
+                             d: int, d_out: int, cap: int,
+                             stream: int = 0) -> int:
+        """solve_device that allocates nothing (tiled path, fixed device
+        scratch); same arguments and errors."""
+        cnt = ctypes.c_size_t(0)
+        rc = self._lib.pms_solve_device_noalloc(
+            self._h, ctypes.c_void_p(d_seqs), n, m, l, d,
+            ctypes.c_void_p(stream), ctypes.c_void_p(d_out), cap,
+            ctypes.byref(cnt))
+        if rc == PMS_ENOMEM and cnt.value > 0:
             err = PmsError(rc, self._lib.pms_last_error(self._h).decode())
             err.needed = cnt.value
             raise err

@@ -375,7 +375,8 @@ namespace pms {
 // d_out_ext (cap_ext codes) if given, else in ctx-owned memory.
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,
-               size_t cap_ext, int forced_path, SolveOut *res, int q)
+               size_t cap_ext, int forced_path, SolveOut *res, int q,
+               const FixedArena *fixed)
 {
     const double t0 = now_ms();
     res->d_out = nullptr;
@@ -397,7 +398,16 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                            "only");
         forced_path = PMS_PATH_TILED;
     }
+    if (fixed) {
+        if (quorum || !d_out_ext)
+            return c->fail(PMS_EINVAL, "fixed scratch: plain solves into a "
+                           "caller buffer only");
+        forced_path = PMS_PATH_TILED;
+    }
     Plan P = c->plan(n, m, l, d, forced_path);
+    if (fixed && P.path != PMS_PATH_TILED)
+        return c->fail(PMS_EINVAL, "fixed scratch: l=%d is outside the tiled "
+                       "path (3 <= l, at most 4^%d tiles)", l, kMaxTilePrefix);
     if (quorum) {
         P.s = std::min(P.s, kQuorumMaxSuffix);
         if (l < 3 || P.s < 3 || l - P.s > kMaxTilePrefix)
@@ -424,6 +434,19 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         if (hn != c->heap_need.end())
             heap_cap = std::max(heap_cap, hn->second);
     }
+    if (fixed) {
+        // the heap takes every byte of the scratch that the rest leaves
+        const InstLayout l0 = layout_instance(n, m, l, ntiles, 1, false, true,
+                                              false);
+        const size_t fixed_part = align_up(l0.total) +
+                                  align_up(sizeof(InstDev)) +
+                                  align_up(sizeof(TileStats)) + 256 + 512;
+        if (fixed_part >= fixed->bytes)
+            return c->fail(PMS_ENOMEM, "fixed scratch: the instance needs "
+                           "%zu bytes beside its output heap; the scratch "
+                           "holds %zu", fixed_part, fixed->bytes);
+        heap_cap = 1 + (fixed->bytes - fixed_part) / 8;
+    }
 
     for (int attempt = 0; attempt < 5; attempt++) {
         const bool own_out = (d_out_ext == nullptr) &&
@@ -434,9 +457,17 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         const size_t stats_off = desc_off + align_up(sizeof(InstDev));
         const size_t next_off = stats_off + align_up(sizeof(TileStats));
         const size_t need = next_off + 256;
-        if ((rc = c->alloc(c->arena, need)))
-            return rc;
-        char *base = (char *)c->arena.p;
+        char *base;
+        if (fixed) {
+            if (need > fixed->bytes)
+                return c->fail(PMS_ENOMEM, "fixed scratch: need %zu bytes, "
+                               "the scratch holds %zu", need, fixed->bytes);
+            base = fixed->base;
+        } else {
+            if ((rc = c->alloc(c->arena, need)))
+                return rc;
+            base = (char *)c->arena.p;
+        }
         InstDev I = make_desc(base, lay, d_seqs, n, m, l, d, P.s, P.surv_t,
                               ntiles, heap_cap);
         if (quorum)
@@ -623,12 +654,20 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             if (hp[2] != ~0ull)
                 return c->fail(PMS_EBASE, "bad base in string %llu at offset "
                                "%llu", hp[2] / m, hp[2] % m);
+            if (hp[1] > heap_cap && fixed) {
+                res->count = hp[1];
+                return c->fail(PMS_ENOMEM, "fixed scratch: %llu motifs do not "
+                               "fit its output heap of %llu",
+                               (unsigned long long)hp[1],
+                               (unsigned long long)heap_cap);
+            }
             if (hp[1] > heap_cap) {
                 heap_cap = hp[1] + 1024;
                 S.retries++;
                 continue;
             }
-            c->heap_need[shape_key] = hp[1] + 1024;
+            if (!fixed)
+                c->heap_need[shape_key] = hp[1] + 1024;
             if (hp[0] > dst_cap) {
                 res->count = hp[0];
                 return c->fail(PMS_ENOMEM, "output capacity %llu < %llu",
@@ -871,6 +910,9 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->tb.ball_off = (const int *)(tb + o_off);
     c->tb.m3 = (const unsigned long long *)(tb + o_m3);
     load_tune_cache(c.get());
+    // the no-allocation entry point's scratch array on this device (the
+    // device is current); a failure here is retried at that entry point
+    (void)noalloc_scratch(c->device);
     *out = c.release();
     return PMS_OK;
 }

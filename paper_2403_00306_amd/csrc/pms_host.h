@@ -72,6 +72,13 @@ struct SolveOut {
     size_t count;
 };
 
+// Device memory a solve must work in instead of the context's arena: the
+// tiled path only, no allocation, output in the caller's buffer.
+struct FixedArena {
+    char *base;
+    size_t bytes;
+};
+
 struct Server;
 
 }  // namespace pms
@@ -150,9 +157,16 @@ inline bool pick_wide(const pms_ctx *c, bool automatic)
            (c->opt.tile_threads == 0 && automatic);
 }
 // q = 0 (or q = n): plain PMS; 1 <= q < n: (l,d,q)-motifs (tiled path).
+// fixed != nullptr: work in that memory (tiled path, d_out_ext required),
+// allocate nothing, PMS_ENOMEM when the instance does not fit.
 int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                int n, int m, int l, int d, hipStream_t st, uint64_t *d_out_ext,
-               size_t cap_ext, int forced_path, SolveOut *res, int q = 0);
+               size_t cap_ext, int forced_path, SolveOut *res, int q = 0,
+               const FixedArena *fixed = nullptr);
+// Device address of the fixed scratch array on the context's device,
+// looked up once per device (pms_noalloc.hip); nullptr if unavailable.
+char *noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 // Pair path: lists compatible pairs and filters their candidates into
 // I.heap (index already built on st); *found = survivors, possibly more
 // than I.heap_cap (then nothing beyond it was written).
