@@ -51,6 +51,7 @@ struct __align__(16) TileShared {
     int rpos[kMaxL + 1];
     unsigned long long red64[kMaxTileWaves];
     unsigned int red32[kMaxTileWaves];
+    unsigned int redc[2][kMaxTileWaves];   // pass counts, by pass parity
     unsigned long long bcast;
     uint32_t mass[kOrderMax];          // per-tile string order: sphere mass
     int torder[kOrderMax];             //   of each string, strings by mass
@@ -84,6 +85,41 @@ block_sum64(unsigned long long v, unsigned long long *red)
         red[threadIdx.x >> 6] = v;
     __syncthreads();
     unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++)
+        t += red[w];
+    return uni(t);
+}
+
+// Sum over the wave by DPP (no LDS): inclusive scans of the four rows of
+// 16 lanes (row_shr 1, 2, 4, 8), then row 0's total into row 1 and row 2's
+// into row 3 (row_bcast:15), then lane 31's into rows 2 and 3
+// (row_bcast:31); lane 63 holds the sum. Lanes whose source is outside
+// the row, or rows the mask leaves out, add the 0 passed as `old`.
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Sum over the workgroup with one barrier: the caller alternates between
+// two `red` buffers on successive calls, and at least one other barrier
+// separates a call from the next use of the same buffer, so no thread can
+// overwrite a value another thread has yet to read.
+template <int TPB>
+__device__ __forceinline__ uint32_t block_sum32(uint32_t v, unsigned int *red)
+{
+    constexpr int kWaves = TPB / 64;
+    v = wave_sum32(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t t = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; w++)
         t += red[w];
@@ -132,18 +168,9 @@ __device__ __forceinline__ void prefix_planes(uint64_t P, int pl,
     }
 }
 
-// LDS position of tile word w: the bank bits (low 5 bits of the word
-// position) take the XOR of the word index's low 5 bits with its higher
-// bit groups, so words that differ only in high digits still fall in
-// different banks. A bijection on [0, 4^q) that keeps bits 5 and up.
-__device__ __forceinline__ uint32_t wpos(uint32_t w)
-{
-    return w ^ ((w >> 5) & 31u) ^ ((w >> 10) & 31u);
-}
-
-// wpos is linear over GF(2) (shifts, masks and XORs of bits), so
-// wpos(y ^ m) = wpos(y) ^ wpos(m): a lane keeps its XOR mask's part of the
-// LDS address, and an l-mer's part is computed once when it is listed.
+// Tile words sit at LDS position wpos(w) (pms_internal.h). wpos is linear,
+// so wpos(y ^ m) = wpos(y) ^ wpos(m): a lane keeps its XOR mask's part of
+// the LDS address, and an l-mer's part is computed once when it is listed.
 // A listed l-mer is a = (wpos(word index) << 6) | (last 3 bases); the byte
 // offset of its word is ((a >> 3) & ~7), of the 32-bit half that holds its
 // bit ((a >> 3) & ~3).
@@ -192,11 +219,17 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
     const PlaneRow yp = planes_row(I.planes, (size_t)seq * I.L);
     const g_u64 *yc = gptr(I.codes) + (size_t)seq * I.L;
     const uint32_t sufmask = (1u << (2 * s)) - 1u;
-    const int *boff = tb.ball_off + q * 8;
-    // ball table q (read-only): each lane reads its entry once per class
-    const __attribute__((address_space(4))) uint16_t *ball =
-        (const __attribute__((address_space(4))) uint16_t *)(const void *)(
-            tb.ball + tb.ball_base[q]);
+    // read-only tables through the constant address space: the uniform
+    // reads (sphere sizes, group constants) become scalar loads
+    typedef const __attribute__((address_space(4))) uint32_t c_u32;
+    typedef const __attribute__((address_space(4))) int c_i32;
+    c_i32 *boff = (c_i32 *)(const void *)(tb.ball_off + q * 8);
+    c_u32 *grp = (c_u32 *)(const void *)(tb.grp + (TPB >= kTPBWide ? 1 : 0) *
+                                                        kGrpStride +
+                                         q * 16);
+    // ball table q: each lane reads its entry once per class
+    c_u32 *ball = (c_u32 *)(const void *)(
+        tb.ball32 + ((c_i32 *)(const void *)tb.ball_base)[q]);
     unsigned long long marks = 0;
     for (int y0 = 0; y0 < I.L; y0 += kYChunk) {
         const int ny = min(kYChunk, I.L - y0);
@@ -272,8 +305,8 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     uint32_t e = e0 + lane;
                     e = e < bs ? e : e - (eb ? (uint32_t)kTPB : bs);
                     const uint32_t ent = ball[e];
-                    const uint32_t lc = 8u * wpos(ent & 0xfffu);
-                    const int tt = min(r - (int)(ent >> 12), 3);
+                    const uint32_t lc = ent & 0xffffu;
+                    const int tt = min(r - (int)(ent >> 16), 3);
                     const unsigned long long *mt = sh.m3 + tt;
                     const bool single = __ballot(tt != 0) == 0;
                     for (int y0c = 0; y0c < c; y0c += 64) {
@@ -331,15 +364,16 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 }
             } else {
                 // G = kTPB/bs groups of bs lanes: each lane owns one entry
-                // and its group walks every G-th l-mer of the class
+                // and its group walks every G-th l-mer of the class (the
+                // division by bs is a multiply by a host-made constant)
                 const uint32_t vt = ((uint32_t)tid + rot) & (uint32_t)(kTPB - 1);
-                const uint32_t G = (uint32_t)kTPB / bs;
-                const uint32_t slot = vt / bs;
+                const uint32_t G = grp[rw * 2];
+                const uint32_t slot = (vt * grp[rw * 2 + 1]) >> kGrpShift;
                 const uint32_t e = vt - slot * bs;
                 if (slot < G) {
                     const uint32_t ent = ball[e];
-                    const uint32_t lc = 8u * wpos(ent & 0xfffu);
-                    const uint32_t tt = (uint32_t)min(r - (int)(ent >> 12), 3);
+                    const uint32_t lc = ent & 0xffffu;
+                    const uint32_t tt = (uint32_t)min(r - (int)(ent >> 16), 3);
                     const unsigned long long *mt = sh.m3 + tt;
                     uint32_t yi = slot;
                     if (__ballot(tt != 0) == 0) {
@@ -374,9 +408,26 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
     return marks;
 }
 
-// Write the set bits of the tile (words in sh.U) as ascending codes to
-// dst[0..). Thread t owns a contiguous block of words so that thread order
-// is code order. Codes: (tile << 2s) | (word << 6) | bit.
+// The codes of the set bits of words w0..w1 of sh.U, ascending, written
+// to dst[pos..). Codes: (tile << 2s) | (word << 6) | bit.
+__device__ __forceinline__ void emit_bits(const TileShared &sh, int w0,
+                                          int w1, uint64_t tile, int s,
+                                          uint64_t *dst, unsigned int pos)
+{
+    const uint64_t base = tile << (2 * s);
+    for (int w = w0; w < w1; w++) {
+        unsigned long long v = sh.U[w];
+        while (v) {
+            const int b = __ffsll(v) - 1;
+            v &= v - 1;
+            dst[pos++] = base | ((uint64_t)w << 6) | (uint64_t)b;
+        }
+    }
+}
+
+// Write the set bits of the tile (words 0..W-1 of sh.U) as ascending codes
+// to dst[0..). Thread t owns a contiguous block of words so that thread
+// order is code order.
 template <int TPB>
 __device__ void emit_words(const TileShared &sh, int W, uint64_t tile, int s,
                            uint64_t *dst, bool write, unsigned int *red)
@@ -393,15 +444,40 @@ __device__ void emit_words(const TileShared &sh, int W, uint64_t tile, int s,
     unsigned int pos = block_exscan<TPB>(cnt, red, &tot);
     if (!write)
         return;
-    const uint64_t base = tile << (2 * s);
-    for (int w = w0; w < w1; w++) {
-        unsigned long long v = sh.U[w];
-        while (v) {
-            const int b = __ffsll(v) - 1;
-            v &= v - 1;
-            dst[pos++] = base | ((uint64_t)w << 6) | (uint64_t)b;
-        }
+    emit_bits(sh, w0, w1, tile, s, dst, pos);
+}
+
+// Emit tile g's codes (words 0..W-1 of sh.U) into the instance's heap: the
+// count comes from the same scan that places the codes, so the space taken
+// from heap_top always matches what is written. Records the tile's count
+// and heap offset; writes nothing once the heap is full (heap_top then
+// tells the host how much it needed). Returns the count.
+template <int TPB>
+__device__ unsigned int emit_tile(TileShared &sh, int W, uint64_t tile,
+                                  uint64_t g, int s, const InstDev &I)
+{
+    constexpr int kTPB = TPB;
+    const int tid = threadIdx.x;
+    const int per = (W + kTPB - 1) / kTPB;
+    const int w0 = tid * per;
+    const int w1 = min(w0 + per, W);
+    unsigned int cnt = 0;
+    for (int w = w0; w < w1; w++)
+        cnt += __popcll(sh.U[w]);
+    unsigned int tot;
+    const unsigned int pos = block_exscan<TPB>(cnt, sh.red32, &tot);
+    if (tid == 0) {
+        const unsigned long long off =
+            tot ? atomicAdd(I.heap_top, (unsigned long long)tot) : 0ull;
+        sh.bcast = off;
+        I.tile_cnt[g] = tot;
+        I.tile_heap_off[g] = off;
     }
+    __syncthreads();
+    const unsigned long long off = uni(sh.bcast);
+    if (off + tot <= I.heap_cap)
+        emit_bits(sh, w0, w1, tile, s, I.heap + off, pos);
+    return tot;
 }
 
 // Convert a code (first base in the top digit) to bit planes.
@@ -503,8 +579,12 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         __syncthreads();
     }
 
+    // the running intersection; every code is in it before the first string
     unsigned long long A[kWordsPerThread];
-    unsigned long long total = 0;
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; k++)
+        A[k] = ~0ull;
+    uint32_t total = 0;
     int si = 0;
     bool to_filter = false;
     for (si = 0; si < I.n; si++) {
@@ -513,7 +593,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         // pass's AND step, or after the previous tile's emission
         const unsigned long long mk = mark_string<TPB>(I, seq, Phi, Plo, premask,
                                                   sh, tb);
-        unsigned long long cnt = 0;
+        uint32_t cnt = 0;
         // word tid + k*kTPB sits at wpos(tid) ^ wpos(k*kTPB) (wpos is
         // XOR-linear, the two parts share no bits); the base is made opaque
         // per pass so that the compiler does not hold one address per word
@@ -530,18 +610,19 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 const unsigned long long u = __hip_atomic_exchange(
                     &sh.U[pw], 0ull, __ATOMIC_RELAXED,
                     __HIP_MEMORY_SCOPE_WORKGROUP);
-                A[k] = (si == 0) ? u : (A[k] & u);
-                cnt += __popcll(A[k]);
+                A[k] &= u;
+                cnt += (uint32_t)__popcll(A[k]);
             }
         }
-        total = block_sum64<TPB>(cnt, sh.red64);
+        // at most 4^9 codes: the count fits in 32 bits
+        total = block_sum32<TPB>(cnt, sh.redc[acc.passes & 1]);
         // work counters: every thread adds the same (uniform) amounts, so
         // they stay in scalar registers (thread 0 flushes them at the end)
         acc.passes++;
         acc.marks += mk;
         if (total == 0)
             break;
-        if (total <= (unsigned long long)I.surv_t && si + 1 < I.n) {
+        if (total <= (uint32_t)I.surv_t && si + 1 < I.n) {
             to_filter = true;
             break;
         }
@@ -564,16 +645,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 sh.U[w] = A[k];
         }
         __syncthreads();
-        if (tid == 0) {
-            const unsigned long long off = atomicAdd(heap_top, total);
-            sh.bcast = off;
-            tile_cnt[g] = (uint32_t)total;
-            tile_heap_off[g] = off;
-        }
-        __syncthreads();
-        const unsigned long long off = uni(sh.bcast);
-        const bool fits = off + total <= heap_cap;
-        emit_words<TPB>(sh, W, t, s, heap + (fits ? off : 0), fits, sh.red32);
+        emit_tile<TPB>(sh, W, t, g, s, I);
         __syncthreads();
         for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
             sh.U[w] = 0;
@@ -610,7 +682,10 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
         for (int k = 0; k < kWordsPerThread; k++) {
             const int w = tid + k * kTPB;
             unsigned long long v = (w < W) ? A[k] : 0ull;
-            while (v) {
+            // (pos < kSurvMax always: the pass count that sent the tile
+            // here is the same number; the bound only keeps the writes in
+            // the buffer whatever happens)
+            while (v && pos < (unsigned int)kSurvMax) {
                 const int b = __ffsll(v) - 1;
                 v &= v - 1;
                 const uint64_t code = base | ((uint64_t)w << 6) | (uint64_t)b;
@@ -619,7 +694,7 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 pos++;
             }
         }
-        N = (int)nt;
+        N = (int)min(nt, (unsigned int)kSurvMax);
     }
     auto seq_at = [&](int j) {
         return tile_order ? uni(sh.torder[j]) : uni(I.order[j]);
@@ -802,26 +877,14 @@ __device__ void run_tile_quorum(const InstDev &I, uint64_t t, TileShared &sh,
         }
         return;
     }
-    unsigned long long cnt = 0;
 #pragma unroll
     for (int k = 0; k < kQWords; k++) {
         const int w = tid + k * kTPB;
-        if (w < W) {
+        if (w < W)
             sh.U[w] = live[k];
-            cnt += __popcll(live[k]);
-        }
-    }
-    const unsigned long long total = block_sum64<TPB>(cnt, sh.red64);
-    if (tid == 0) {
-        const unsigned long long off = atomicAdd(I.heap_top, total);
-        sh.bcast = off;
-        I.tile_cnt[t] = (uint32_t)total;
-        I.tile_heap_off[t] = off;
     }
     __syncthreads();
-    const unsigned long long off = uni(sh.bcast);
-    const bool fits = off + total <= I.heap_cap;
-    emit_words<TPB>(sh, W, t, s, I.heap + (fits ? off : 0), fits, sh.red32);
+    emit_tile<TPB>(sh, W, t, t, s, I);
     __syncthreads();
     for (int w = tid; w < W; w += kTPB)   // U is zero for the next tile
         sh.U[w] = 0;

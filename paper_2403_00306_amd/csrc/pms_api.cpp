@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 using namespace pms;
@@ -303,7 +304,9 @@ Plan pms_ctx::plan(int n, int m, int l, int d, int forced)
 namespace {
 
 void build_tables(std::vector<uint16_t> &ball, std::vector<int> &base,
-                  std::vector<int> &off, std::vector<unsigned long long> &m3)
+                  std::vector<int> &off, std::vector<uint32_t> &ball32,
+                  std::vector<uint32_t> &grp,
+                  std::vector<unsigned long long> &m3)
 {
     ball.clear();
     base.assign(8, 0);
@@ -344,6 +347,25 @@ void build_tables(std::vector<uint16_t> &ball, std::vector<int> &base,
                     break;
             }
         }
+    }
+    ball32.resize(ball.size());
+    for (size_t i = 0; i < ball.size(); i++)
+        ball32[i] = 8u * wpos(ball[i] & 0xfffu) | (uint32_t)(ball[i] >> 12)
+                                                      << 16;
+    grp.assign(2 * kGrpStride, 0);
+    for (int set = 0; set < 2; set++) {
+        const uint32_t tpb = set ? 512u : 256u;
+        for (int q = 0; q <= kBallDigits; q++)
+            for (int rw = 0; rw <= q; rw++) {
+                const uint32_t bs = (uint32_t)off[q * 8 + rw + 1];
+                const uint32_t mg = ((1u << kGrpShift) + bs - 1) / bs;
+                for (uint32_t v = 0; v < 1024; v++)
+                    if ((v * mg) >> kGrpShift != v / bs)
+                        abort();   // the multiplier must divide exactly
+                uint32_t *g = &grp[set * kGrpStride + (q * 8 + rw) * 2];
+                g[0] = tpb / bs;
+                g[1] = mg;
+            }
     }
     m3.assign(256, 0);
     for (int b = 0; b < 64; b++)
@@ -881,12 +903,15 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     }
     std::vector<uint16_t> ball;
     std::vector<int> bbase, boff;
+    std::vector<uint32_t> ball32, grp;
     std::vector<unsigned long long> m3;
-    build_tables(ball, bbase, boff, m3);
+    build_tables(ball, bbase, boff, ball32, grp, m3);
     const size_t o_ball = 0;
     const size_t o_base = align_up(ball.size() * 2);
     const size_t o_off = o_base + align_up(bbase.size() * 4);
-    const size_t o_m3 = o_off + align_up(boff.size() * 4);
+    const size_t o_b32 = o_off + align_up(boff.size() * 4);
+    const size_t o_grp = o_b32 + align_up(ball32.size() * 4);
+    const size_t o_m3 = o_grp + align_up(grp.size() * 4);
     const size_t tbytes = o_m3 + align_up(m3.size() * 8);
     if (hipMalloc(&c->tables_mem, tbytes) != hipSuccess) {
         g_create_error = "hipMalloc(tables) failed";
@@ -900,6 +925,10 @@ int pms_create(pms_ctx **out, const pms_options *opt)
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(tb + o_off, boff.data(), boff.size() * 4,
                   hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(tb + o_b32, ball32.data(), ball32.size() * 4,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(tb + o_grp, grp.data(), grp.size() * 4,
+                  hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(tb + o_m3, m3.data(), m3.size() * 8,
                   hipMemcpyHostToDevice) != hipSuccess) {
         g_create_error = "table upload failed";
@@ -908,6 +937,8 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->tb.ball = (const uint16_t *)(tb + o_ball);
     c->tb.ball_base = (const int *)(tb + o_base);
     c->tb.ball_off = (const int *)(tb + o_off);
+    c->tb.ball32 = (const uint32_t *)(tb + o_b32);
+    c->tb.grp = (const uint32_t *)(tb + o_grp);
     c->tb.m3 = (const unsigned long long *)(tb + o_m3);
     load_tune_cache(c.get());
     // the no-allocation entry point's scratch array on this device (the

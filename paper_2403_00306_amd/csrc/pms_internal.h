@@ -128,6 +128,24 @@ struct TileStats {
     unsigned long long tiles;       // tiles finished
 };
 
+// LDS position of tile word w: the bank bits (low 5 bits of the word
+// position) take the XOR of the word index's low 5 bits with its higher
+// bit groups, so words that differ only in high digits still fall in
+// different banks. A bijection on [0, 4^q) that keeps bits 5 and up. It is
+// linear over GF(2) (shifts, masks and XORs of bits), so
+// wpos(y ^ m) = wpos(y) ^ wpos(m).
+__host__ __device__ __forceinline__ uint32_t wpos(uint32_t w)
+{
+    return w ^ ((w >> 5) & 31u) ^ ((w >> 10) & 31u);
+}
+
+// Group constants of the small-sphere marking: for a workgroup of TPB
+// threads (256: set 0, 512: set 1) and a word-level sphere of bs entries,
+// G = TPB / bs groups of bs lanes, and a multiplier mg with
+// floor(v / bs) = (v * mg) >> 22 for every v < 1024.
+constexpr int kGrpStride = 7 * 8 * 2;   // per set: (q*8 + rw) * 2 + {G, mg}
+constexpr int kGrpShift = 22;
+
 // Tables built once per context (device memory).
 struct Tables {
     // Word-index ball table for q = s-3 digits: all 4^q XOR masks over q
@@ -137,6 +155,11 @@ struct Tables {
     const uint16_t *ball;        // concatenated for q = 0..6
     const int *ball_base;        // start of table q in ball[]
     const int *ball_off;         // 7 x 8 offsets
+    // The same entries in the form the marking loops use:
+    // 8 * wpos(mask) | weight << 16 (the byte offset of the masked word's
+    // part of an LDS address, and the weight).
+    const uint32_t *ball32;
+    const uint32_t *grp;         // 2 sets x kGrpStride group constants
     // Word masks: m3[b*4 + t] = bit z set iff the 3-base codes z and b
     // differ in at most t bases (t = 3: every z).
     const unsigned long long *m3;
