@@ -3,9 +3,10 @@
 Every case compares the ascending uint64 motif codes element by element with
 the oracle on the same seeded input. Small cases span many tiles and a
 ragged tail; the full (9,2) and (13,4) configurations are compared whole;
-(17,6) is checked on properties the oracle can verify at any size (every
-reported code, the plant, path agreement, and completeness on a sample of
-reference l-mers). Integer results: the tolerance is zero.
+(17,6) is compared whole with stored oracle sets (seeds 1-5) and also
+checked on properties the oracle can verify at any size (every reported
+code, the plant, path agreement, and completeness on a sample of reference
+l-mers). Integer results: the tolerance is zero.
 """
 import os
 import random
@@ -154,19 +155,28 @@ def load_golden(name, seed):
         if line.strip() and not line.startswith("#"):
             k, v = [t.strip() for t in line.split("=", 1)]
             kv[k] = v
-    return kv, np.array([int(x) for x in kv["motifs"].split(",")],
+    return kv, np.array([int(x) for x in kv["motifs"].split(",") if x],
                         dtype=np.uint64)
 
 
-@pytest.mark.parametrize("name,seed", [("pms_9_2", 1), ("pms_9_2", 2),
-                                       ("pms_9_2", 3), ("pms_13_4", 1)])
+# every seed of the three plain configurations, stored by
+# tests/golden/make_golden.py from the oracle (O1, and O0 where l <= 13)
+GOLDEN_PLAIN = ([("pms_9_2", k) for k in range(1, 6)] +
+                [("pms_13_4", k) for k in range(1, 6)] +
+                [("pms_17_6", k) for k in range(1, 6)])
+
+
+@pytest.mark.parametrize("name,seed", GOLDEN_PLAIN)
 @pytest.mark.parametrize("path", PATHS)
 def test_full_size_golden(name, seed, path):
     kv, want = load_golden(name, seed)
     inst = pmsgen.plain(name, seed)
+    import hashlib
+    assert hashlib.sha256(inst.seqs).hexdigest() == kv["input_sha256"]
     say("full", name, seed, "path", path)
     got, st = solve_path(path, inst.seqs, inst.n, inst.m, inst.l, inst.d)
     np.testing.assert_array_equal(got, want)
+    assert code_of(inst.motif) in set(int(x) for x in got)
     if path == pms.PATH_FILTER:
         assert st["hcanon"] == int(kv["hcanon"])
 

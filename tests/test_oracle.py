@@ -503,8 +503,8 @@ def load_golden(name):
     return kv, motifs
 
 
-@pytest.mark.parametrize("name,seed", [("pms_9_2", 1), ("pms_9_2", 2),
-                                       ("pms_9_2", 3), ("pms_13_4", 1)])
+@pytest.mark.parametrize("name,seed", [("pms_9_2", k) for k in range(1, 6)] +
+                         [("pms_13_4", k) for k in range(1, 6)])
 def test_golden_full_size(name, seed):
     kv, motifs = load_golden("%s_seed%d.txt" % (name, seed))
     inst = pmsgen.plain(name, seed)
@@ -515,3 +515,30 @@ def test_golden_full_size(name, seed):
     assert [int(v) for v in got] == motifs
     assert h == int(kv["hcanon"])
     assert py_code(inst.motif) in motifs
+
+
+@pytest.mark.parametrize("seed", range(1, 6))
+def test_golden_17_6_stored(seed):
+    # the stored (17,6) sets (O1 over all 584 references, minutes of CPU
+    # each) belong to the generator's current stream, hold the plant, and
+    # every stored code is a motif by the direct check of Definition 5;
+    # PMS_SLOW=1 recomputes them whole
+    import hashlib
+    kv, motifs = load_golden("pms_17_6_seed%d.txt" % seed)
+    inst = pmsgen.plain("pms_17_6", seed)
+    assert hashlib.sha256(inst.seqs).hexdigest() == kv["input_sha256"]
+    assert int(kv["count"]) == len(motifs) and motifs == sorted(set(motifs))
+    assert py_code(inst.motif) in motifs
+    for c in motifs:
+        assert oracle.is_motif(inst.seqs, inst.n, inst.m, inst.l, inst.d, c)
+    assert int(kv["hcanon"]) > 5e12
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("seed", range(1, 6))
+def test_golden_17_6_recompute(seed):
+    kv, motifs = load_golden("pms_17_6_seed%d.txt" % seed)
+    inst = pmsgen.plain("pms_17_6", seed)
+    got, h = oracle.o1(inst.seqs, inst.n, inst.m, inst.l, inst.d)
+    assert [int(v) for v in got] == motifs
+    assert h == int(kv["hcanon"])
