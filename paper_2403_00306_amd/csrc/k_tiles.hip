@@ -52,6 +52,7 @@ struct __align__(16) TileShared {
     unsigned long long red64[kMaxTileWaves];
     unsigned int red32[kMaxTileWaves];
     unsigned int redc[2][kMaxTileWaves];   // pass counts, by pass parity
+    unsigned long long hitm[2][kSurvMax / 64];   // filter stage hits
     unsigned long long bcast;
     uint32_t mass[kOrderMax];          // per-tile string order: sphere mass
     int torder[kOrderMax];             //   of each string, strings by mass
@@ -217,12 +218,13 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
     const int tid = threadIdx.x;
     const int d = I.d, s = I.s, q = s - 3;
     const PlaneRow yp = planes_row(I.planes, (size_t)seq * I.L);
-    const g_u64 *yc = gptr(I.codes) + (size_t)seq * I.L;
     const uint32_t sufmask = (1u << (2 * s)) - 1u;
     // read-only tables through the constant address space: the uniform
     // reads (sphere sizes, group constants) become scalar loads
     typedef const __attribute__((address_space(4))) uint32_t c_u32;
     typedef const __attribute__((address_space(4))) int c_i32;
+    // low words of the string's l-mer codes (the suffix fits in 18 bits)
+    c_u32 *ycl = (c_u32 *)(const void *)(I.codes + (size_t)seq * I.L);
     c_i32 *boff = (c_i32 *)(const void *)(tb.ball_off + q * 8);
     c_u32 *grp = (c_u32 *)(const void *)(tb.grp + (TPB >= kTPBWide ? 1 : 0) *
                                                         kGrpStride +
@@ -243,11 +245,14 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
             const int j = tid + u * kTPB;
             rr[u] = -1;
             if (j < ny) {
+                // both loads in flight together: one memory round trip
                 const uint2 y = yp[y0 + j];
+                const uint32_t yl = ycl[2 * (y0 + j)];
+                asm volatile("" : : "v"(yl));
                 const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
                 if (k <= d) {
                     rr[u] = d - k;
-                    ys[u] = list_entry((uint32_t)yc[y0 + j] & sufmask);
+                    ys[u] = list_entry(yl & sufmask);
                     atomicAdd(&sh.rcnt[d - k], 1);
                 }
             }
@@ -269,13 +274,17 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                 sh.ylist[atomicAdd(&sh.rpos[rr[u]], 1)] = ys[u];
         __syncthreads();
         const uint32_t lane = (uint32_t)tid & 63u;
+        // every class's count and list offset in one read per lane (d < 32),
+        // then taken per class by readlane
+        const int vcnt = (int)lane <= d ? sh.rcnt[lane] : 0;
+        const int voff = (int)lane <= d ? sh.roff[lane] : 0;
         for (int r = 0; r <= d; r++) {
-            const int c = uni(sh.rcnt[r]);
+            const int c = __builtin_amdgcn_readlane(vcnt, r);
             if (c == 0)
                 continue;
             const int rw = min(r, q);
             const uint32_t bs = (uint32_t)boff[rw + 1];
-            const uint32_t *yl = sh.ylist + uni(sh.roff[r]);
+            const uint32_t *yl = sh.ylist + __builtin_amdgcn_readlane(voff, r);
             marks += (unsigned long long)c * bs;
             // rotate the lane assignment per class so that the lanes a
             // class leaves idle fall in a different wave each time
@@ -375,30 +384,37 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
                     const uint32_t lc = ent & 0xffffu;
                     const uint32_t tt = (uint32_t)min(r - (int)(ent >> 16), 3);
                     const unsigned long long *mt = sh.m3 + tt;
-                    uint32_t yi = slot;
+                    // the group's l-mers are a contiguous block, read four
+                    // at a time (class lists start 4-aligned and are padded
+                    // to a multiple of 4; entries past the block are not
+                    // marked)
+                    uint32_t blk = 4;
+                    while (blk * G < (uint32_t)c)
+                        blk += 4;
+                    const uint32_t b0 = slot * blk;
+                    const uint32_t b1 = min((uint32_t)c, b0 + blk);
+                    const uint4 *yl4 = reinterpret_cast<const uint4 *>(yl);
                     if (__ballot(tt != 0) == 0) {
                         // in-word radius 0 in every active lane: single bit
-                        for (; yi + G < (uint32_t)c; yi += 2 * G) {
-                            const uint32_t a0 = yl[yi], a1 = yl[yi + G];
-                            or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
-                            or32_at(sh, ((a1 >> 3) & ~3u) ^ lc, 1u << (a1 & 31u));
-                        }
-                        if (yi < (uint32_t)c) {
-                            const uint32_t a0 = yl[yi];
-                            or32_at(sh, ((a0 >> 3) & ~3u) ^ lc, 1u << (a0 & 31u));
+                        for (uint32_t b = b0; b < b1; b += 4) {
+                            const uint4 v4 = yl4[b >> 2];
+                            const uint32_t av[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                            for (uint32_t k = 0; k < 4; k++)
+                                if (b + k < b1)
+                                    or32_at(sh, ((av[k] >> 3) & ~3u) ^ lc,
+                                            1u << (av[k] & 31u));
                         }
                         continue;
                     }
-                    for (; yi + G < (uint32_t)c; yi += 2 * G) {
-                        const uint32_t a0 = yl[yi], a1 = yl[yi + G];
-                        const unsigned long long m0 = mt[(a0 & 63u) * 4u];
-                        const unsigned long long m1 = mt[(a1 & 63u) * 4u];
-                        or64_at(sh, ((a0 >> 3) & ~7u) ^ lc, m0);
-                        or64_at(sh, ((a1 >> 3) & ~7u) ^ lc, m1);
-                    }
-                    if (yi < (uint32_t)c) {
-                        const uint32_t a0 = yl[yi];
-                        or64_at(sh, ((a0 >> 3) & ~7u) ^ lc, mt[(a0 & 63u) * 4u]);
+                    for (uint32_t b = b0; b < b1; b += 4) {
+                        const uint4 v4 = yl4[b >> 2];
+                        const uint32_t av[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                        for (uint32_t k = 0; k < 4; k++)
+                            if (b + k < b1)
+                                or64_at(sh, ((av[k] >> 3) & ~7u) ^ lc,
+                                        mt[(av[k] & 63u) * 4u]);
                     }
                 }
             }
@@ -665,8 +681,6 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     uint2 *const plb0 = reinterpret_cast<uint2 *>(sh.U);
     uint2 *const plb1 = plb0 + kSurvMax;
     uint64_t *const cdb1 = reinterpret_cast<uint64_t *>(sh.U) + 2 * kSurvMax;
-    uint32_t *const hitf = reinterpret_cast<uint32_t *>(
-        reinterpret_cast<uint64_t *>(sh.U) + 3 * kSurvMax);
     const int L = I.L;
     int N;
     {
@@ -699,26 +713,33 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     auto seq_at = [&](int j) {
         return tile_order ? uni(sh.torder[j]) : uni(I.order[j]);
     };
-    // l-mers r0 + tid + u*kTPB of string `sq`; past the end, the last l-mer
-    // again (a repeat leaves every minimum unchanged)
+    // l-mers of a round: lane t holds l-mers r0 + kFiltPer*t + u, so that
+    // they fill the first ceil(L/kFiltPer) lanes and the waves past them
+    // skip the round; past the end, the last l-mer again (a repeat leaves
+    // every minimum unchanged)
     auto load_ys = [&](int sq, int r0, uint2 (&y)[kFiltPer]) {
         const uint2 *row = I.planes + (size_t)sq * (size_t)L;
 #pragma unroll
         for (int u = 0; u < kFiltPer; u++)
-            y[u] = row[min(r0 + tid + u * kTPB, L - 1)];
+            y[u] = row[min(r0 + kFiltPer * tid + u, L - 1)];
     };
     constexpr int kRound = kFiltPer * kTPB;
+    constexpr int kMaskWords = kSurvMax / 64;
     const int rounds = (L + kRound - 1) / kRound;
     const int lane = tid & 63;
+    const int wid = uni(tid >> 6);
     uint2 y[kFiltPer];
     if (si + 1 < I.n)
         load_ys(seq_at(si + 1), 0, y);
-    __syncthreads();   // the list is complete
+    if (tid < 2 * kMaskWords)
+        (&sh.hitm[0][0])[tid] = 0ull;
+    __syncthreads();   // the list is complete, the hit masks are clear
     int cur = 0;
     for (int sj = si + 1; sj < I.n && N > 0; sj++) {
         acc.ftests += (unsigned long long)N * (unsigned long long)L;
         const uint2 *plc = cur ? plb1 : plb0;
         const uint64_t *cdc = cur ? cdb1 : sh.surv;
+        const int par = (sj - si - 1) & 1;
         for (int r = 0; r < rounds; r++) {
             // the next load: this string's next round, else the next
             // string's first
@@ -727,43 +748,78 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                 load_ys(seq_at(sj), (r + 1) * kRound, yn);
             else if (sj + 1 < I.n)
                 load_ys(seq_at(sj + 1), 0, yn);
-            for (int c0 = 0; c0 < N; c0 += 4) {
-                uint2 cp[4];
+            // a wave whose lanes hold no l-mer of this round has nothing
+            // to test
+            if (r * kRound + kFiltPer * 64 * wid < L) {
+                // the codes in blocks of 64: bit v of hm = some lane of the
+                // wave has an l-mer within d of code kb*64 + v
+                for (int kb = 0; kb * 64 < N; kb++) {
+                    unsigned long long hm = 0;
+                    const int cend = min(N, kb * 64 + 64);
+                    for (int c0 = kb * 64; c0 < cend; c0 += 4) {
+                        uint2 cp[4];
 #pragma unroll
-                for (int v = 0; v < 4; v++)
-                    cp[v] = plc[min(c0 + v, N - 1)];
+                        for (int v = 0; v < 4; v++)
+                            cp[v] = plc[min(c0 + v, N - 1)];
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    uint32_t h = 255;
+                        for (int v = 0; v < 4; v++) {
+                            uint32_t h = 255;
 #pragma unroll
-                    for (int u = 0; u < kFiltPer; u++)
-                        h = min(h, (uint32_t)__popc((cp[v].x ^ y[u].x) |
-                                                    (cp[v].y ^ y[u].y)));
-                    const unsigned long long b =
-                        __ballot(h <= (uint32_t)I.d);
-                    if (b != 0 && lane == 0)
-                        hitf[min(c0 + v, N - 1)] = 1u;
+                            for (int u = 0; u < kFiltPer; u++)
+                                h = min(h, (uint32_t)__popc((cp[v].x ^ y[u].x) |
+                                                            (cp[v].y ^ y[u].y)));
+                            if (__ballot(h <= (uint32_t)I.d) != 0)
+                                hm |= 1ull << (c0 + v - kb * 64);
+                        }
+                    }
+                    // codes past the end repeated code N-1: drop their bits
+                    const int nv = cend - kb * 64;
+                    if (nv < 64)
+                        hm &= (1ull << nv) - 1ull;
+                    if (lane == 0 && hm != 0)
+                        atomicOr(&sh.hitm[par][kb], hm);
                 }
             }
 #pragma unroll
             for (int u = 0; u < kFiltPer; u++)
                 y[u] = yn[u];
         }
-        __syncthreads();   // every wave's flags are in
-        bool keep = false;
+        __syncthreads();   // every wave's hits are in
+        // the codes with a hit stay, in their order: a code's new index is
+        // the number of kept codes before it
+        unsigned long long mk[kMaskWords];
+        int nkeep = 0;
+#pragma unroll
+        for (int k = 0; k < kMaskWords; k++) {
+            mk[k] = uni(sh.hitm[par][k]);
+            nkeep += __popcll(mk[k]);
+        }
         if (tid < N) {
-            keep = hitf[tid] != 0u;
-            hitf[tid] = 0u;
+            const int kw = tid >> 6;
+            const unsigned long long below = (1ull << (tid & 63)) - 1ull;
+            int pos = 0;
+            bool keep = false;
+#pragma unroll
+            for (int k = 0; k < kMaskWords; k++) {
+                if (k < kw)
+                    pos += __popcll(mk[k]);
+                if (k == kw) {
+                    pos += __popcll(mk[k] & below);
+                    keep = (mk[k] >> (tid & 63)) & 1ull;
+                }
+            }
+            if (keep) {
+                (cur ? plb0 : plb1)[pos] = plc[tid];
+                (cur ? sh.surv : cdb1)[pos] = cdc[tid];
+            }
         }
-        unsigned int nkeep;
-        const unsigned int pos = block_exscan<TPB>(keep ? 1u : 0u, sh.red32, &nkeep);
-        if (keep) {
-            (cur ? plb0 : plb1)[pos] = plc[tid];
-            (cur ? sh.surv : cdb1)[pos] = cdc[tid];
-        }
+        // the other string parity's masks were last read before this
+        // string started: clear them for the next string
+        if (tid < kMaskWords)
+            sh.hitm[par ^ 1][tid] = 0ull;
         __syncthreads();
         cur ^= 1;
-        N = (int)nkeep;
+        N = nkeep;
     }
     // the survivors into the heap, each at its rank among them by code
     const uint64_t *cdc = cur ? cdb1 : sh.surv;
@@ -1032,42 +1088,79 @@ int tiled_blocks_per_cu(bool wide)
 
 // ---- memory-heavy bitset path ---------------------------------------------
 
-__global__ __launch_bounds__(kTPB, 4) void
-k_bitset_pass(const InstDev *inst, int pass, Tables tb,
-              unsigned long long *A, uint8_t *alive, TileStats *stats)
+// One string pass of the memory-heavy path over every live tile. A tile's
+// words of the resident intersection A are loaded into registers before
+// its sphere union is marked in LDS, so the device-memory latency overlaps
+// the marking; then A &= U is written back (U read and cleared in one LDS
+// instruction) and the tile's liveness recorded for the next pass. Tiles
+// are taken in chunks of kBitsetChunk from a counter, so that workgroups
+// stay balanced as tiles die out.
+constexpr int kBitsetChunk = 8;
+
+template <int TPB>
+__device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
+                            unsigned long long *A, uint8_t *alive,
+                            unsigned int *next, TileStats *stats)
 {
+    constexpr int kTPB = TPB;
+    constexpr int kPer = kMaxWords / TPB;   // words of A per thread
     __shared__ TileShared sh;
-    const InstDev I = *inst;
+    __shared__ unsigned int s_chunk;
+    const InstDev I = uni_desc(*inst);
     const int tid = threadIdx.x;
     const int s = I.s, q = s - 3, pl = I.l - s;
     const int W = 1 << (2 * q);
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
-    const int seq = I.order[pass];
+    const int seq = uni(I.order[pass]);
     for (int i = tid; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
-
+    for (int i = tid; i < kMaxWords; i += kTPB)
+        sh.U[i] = 0;
     unsigned long long marks = 0, passes = 0;
-    for (uint64_t t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
-        if (pass > 0 && !alive[t])
-            continue;
-        for (int w = tid; w < W; w += kTPB)
-            sh.U[w] = 0;
+    const uint64_t nchunks = (I.ntiles + kBitsetChunk - 1) / kBitsetChunk;
+    for (;;) {
         __syncthreads();
-        uint32_t Phi, Plo;
-        prefix_planes(t, pl, Phi, Plo);
-        marks += mark_string<kTPB>(I, seq, Phi, Plo, premask, sh, tb);
-        passes++;
-        unsigned long long *Ag = A + t * (uint64_t)W;
-        int nz = 0;
-        for (int w = tid; w < W; w += kTPB) {
-            const unsigned long long u = sh.U[wpos((uint32_t)w)];
-            const unsigned long long a = pass ? (Ag[w] & u) : u;
-            Ag[w] = a;
-            nz |= (a != 0);
-        }
-        const int any = __syncthreads_or(nz);
         if (tid == 0)
-            alive[t] = (uint8_t)(any != 0);
+            s_chunk = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint64_t ch = uni(s_chunk);
+        if (ch >= nchunks)
+            break;
+        const uint64_t t1 = min((ch + 1) * kBitsetChunk, I.ntiles);
+        for (uint64_t t = ch * kBitsetChunk; t < t1; t++) {
+            if (pass > 0 && alive[t] == 0)
+                continue;
+            unsigned long long *Ag = A + t * (uint64_t)W;
+            unsigned long long a[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const int w = tid + k * kTPB;
+                a[k] = (pass > 0 && w < W) ? Ag[w] : ~0ull;
+            }
+            uint32_t Phi, Plo;
+            prefix_planes(t, pl, Phi, Plo);
+            marks += mark_string<kTPB>(I, seq, Phi, Plo, premask, sh, tb);
+            passes++;
+            int nz = 0;
+            uint32_t tw = (uint32_t)tid;
+            asm volatile("" : "+v"(tw));
+            const uint32_t pbase = wpos(tw);
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const int w = tid + k * kTPB;
+                if (w < W) {
+                    const unsigned long long u = __hip_atomic_exchange(
+                        &sh.U[pbase ^ wpos((uint32_t)(k * kTPB))], 0ull,
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const unsigned long long v = a[k] & u;
+                    Ag[w] = v;
+                    nz |= (v != 0);
+                }
+            }
+            const int any = __syncthreads_or(nz);
+            if (tid == 0)
+                alive[t] = (uint8_t)(any != 0);
+        }
     }
     if (tid == 0 && stats) {
         atomicAdd(&stats->passes, passes);
@@ -1075,13 +1168,32 @@ k_bitset_pass(const InstDev *inst, int pass, Tables tb,
     }
 }
 
+__global__ __launch_bounds__(kTPBWide, kTPBWide / 64) void
+k_bitset_pass(const InstDev *inst, int pass, Tables tb,
+              unsigned long long *A, uint8_t *alive, unsigned int *next,
+              TileStats *stats)
+{
+    bitset_pass<kTPBWide>(inst, pass, tb, A, alive, next, stats);
+}
+
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              TileStats *stats, int grid, hipStream_t st)
+                              unsigned int *next, TileStats *stats, int grid,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPB), 0, st, d_inst,
-                       pass, tb, A, alive, stats);
+    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPBWide), 0, st,
+                       d_inst, pass, tb, A, alive, next, stats);
     return hipGetLastError();
+}
+
+int bitset_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bitset_pass,
+                                                     kTPBWide, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
 }
 
 __global__ __launch_bounds__(kTPB) void

@@ -706,11 +706,15 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                 return rc;
             base = (char *)c->arena.p;
             const int grid = grid_for(c, c->tiled_bpc);
-            for (int pass = 0; pass < n; pass++)
+            for (int pass = 0; pass < n; pass++) {
+                // every pass takes tiles from a counter of its own
+                HIPCHK(c, launch_fill_u64(d_next, 1, 0, st));
                 HIPCHK(c, launch_bitset_pass(d_inst, pass, c->tb,
                                              (unsigned long long *)c->bitset.p,
-                                             (uint8_t *)c->alive.p, d_stats,
-                                             grid, st));
+                                             (uint8_t *)c->alive.p,
+                                             (unsigned int *)d_next, d_stats,
+                                             grid_for(c, c->bitset_bpc), st));
+            }
             S.main_launches = n;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
             HIPCHK(c, launch_bitset_count(d_inst,
@@ -873,6 +877,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->tiled_bpc = tiled_blocks_per_cu();
     c->tiled_wide_bpc = tiled_blocks_per_cu(true);
     c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
+    c->bitset_bpc = bitset_blocks_per_cu();
     c->alpha_bpc = alpha_blocks_per_cu();
     c->pair_bpc = pair_blocks_per_cu();
     c->filter_bpc = filter_blocks_per_cu();

@@ -270,7 +270,9 @@ int tiled_quorum_blocks_per_cu();
 // Memory-heavy bitset path: one pass per string over the whole 4^l space.
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              TileStats *stats, int grid, hipStream_t st);
+                              unsigned int *next, TileStats *stats, int grid,
+                              hipStream_t st);
+int bitset_blocks_per_cu();
 hipError_t launch_bitset_count(const InstDev *d_inst,
                                const unsigned long long *A,
                                const uint8_t *alive, uint32_t *tile_cnt,
