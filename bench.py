@@ -66,15 +66,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# threads the oracle may use: the host's cores, at most the CPU share one
+# GPU's process is given on a shared node (16), and at most OMP_NUM_THREADS
+HOST_SHARE = 16
+
+
 def host_threads() -> int:
     n = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         n = min(n, int(env))
-    return max(1, min(n, 16))
+    return max(1, min(n, HOST_SHARE))
 
 
 def cpu_model() -> str:
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -152,6 +167,9 @@ def cpu_baseline(inst, target_s: float = 12.0) -> dict:
     t = time.perf_counter() - t0
     return {"value": h / t, "unit": "Hamming tests/s", "cores": threads,
             "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "threads_rule": "min(host CPUs, OMP_NUM_THREADS, %d: the CPU "
+                            "share of one GPU's process)" % HOST_SHARE,
             "sample": "sample-driven oracle over the first %d of %d reference "
                       "l-mers of s_1 (same instance), %.1f s, %d tests"
                       % (k, L, t, h)}
@@ -486,6 +504,24 @@ def main():
             "ops_per_launch": alg_ops, "marks": stats["marks"],
             "prefix_tests": stats["tile_passes"] * L,
             "filter_tests": stats["filter_tests"]}
+    # the same kernel against the LDS: its marks are single-bit or mask ORs
+    # into the tile in LDS and every pass reads and clears the tile's words
+    # once; the peak is the device's measured rate of that OR (calibration
+    # kernel at the same occupancy)
+    cal_lds = pms.Context(device=0)
+    lds_peak = cal_lds.lds_rate()
+    cal_lds.close()
+    words_per_tile = 4 ** (stats["tile_suffix"] - 3)
+    lds_ops = stats["marks"] + stats["tile_passes"] * words_per_tile
+    roof_lds = {"bound": "lds", "kernel": tile_kernel(stats),
+                "achieved": lds_ops / (k_ms / 1000.0) / 1e12,
+                "peak": lds_peak / 1e12, "unit": "T lane-ops/s",
+                "frac": lds_ops / (k_ms / 1000.0) / lds_peak,
+                "lane_ops_per_launch": lds_ops,
+                "peak_source": "pms_lds_rate: single-bit LDS atomic ORs, "
+                               "512-thread workgroups, 32 KiB LDS each"}
+    log("lds: %.3g lane-ops/s of %.3g measured peak (%.3f)"
+        % (lds_ops / (k_ms / 1000.0), lds_peak, roof_lds["frac"]))
     f_ops = hcanon * OPS_TEST
     roof_filter = {"bound": "alu", "kernel": "k_filter",
                    "kernel_ms": fst["ms_main"],
@@ -553,7 +589,14 @@ def main():
         log("cpu %.4g tests/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     rec = {"metric": "Hamming tests/s", "value": value,
-           "unit": "Hamming tests/s", "n_gpus": 1, "steps": args.steps,
+           "unit": "Hamming tests/s",
+           "value_kind": "canonical-equivalent: the sample-driven method's "
+                         "exact Hamming-test count H_canon of this instance "
+                         "(counted by the filter path) divided by the "
+                         "fastest exact path's solve time (tiled: marks plus "
+                         "%d executed tests); the filter path's own rate is "
+                         "roofline_filter.tests_per_s" % stats["filter_tests"],
+           "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u32", "data": "synthetic",
@@ -564,7 +607,8 @@ def main():
                       "tile_suffix": stats["tile_suffix"]},
            "solve_ms_17_6": ms_step, "motifs": int(cnt),
            "hcanon": int(hcanon),
-           "roofline": roof, "roofline_filter": roof_filter,
+           "roofline": roof, "roofline_lds": roof_lds,
+           "roofline_filter": roof_filter,
            "cpu_baseline": cpu}
     rec.update(extra)
     if args.copy_probe:

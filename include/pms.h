@@ -279,6 +279,14 @@ double pms_clock_ms(void);
  * the context's stream. Returns PMS_EINVAL for NULL arguments. */
 int pms_test_rate(pms_ctx *ctx, double *tests_per_s);
 
+/* Calibration, not part of any solve: the device's rate of the tile
+ * kernels' mark (a single-bit 32-bit atomic OR into LDS) at their
+ * occupancy, with every half wave on 32 different banks. *ors_per_s
+ * receives lane ORs per second over the whole device. Runs a kernel of
+ * tens of milliseconds on the context's stream. PMS_EINVAL for NULL
+ * arguments. */
+int pms_lds_rate(pms_ctx *ctx, double *ors_per_s);
+
 /* Timing and work counters of the last pms_solve / pms_solve_device /
  * pms_solve_batch call. Kernel times come from HIP events recorded on the
  * stream each kernel ran on. */

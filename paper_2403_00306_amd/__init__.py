@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
                                  P(ctypes.c_double), P(ctypes.c_double)]),
         "pms_clock_ms": (ctypes.c_double, []),
         "pms_test_rate": (i, [vp, P(ctypes.c_double)]),
+        "pms_lds_rate": (i, [vp, P(ctypes.c_double)]),
         "pms_last_stats": (i, [vp, P(Stats)]),
         "pms_serve_stats_get": (i, [vp, P(ServeStats)]),
         "pms_last_hcanon_per_ref": (i, [vp, P(ctypes.c_uint64), sz]),
@@ -410,6 +411,12 @@ class Context:
         r = ctypes.c_double(0.0)
         self._check(self._lib.pms_test_rate(self._h, ctypes.byref(r)))
         return float(r.value)
+
+    def lds_rate(self) -> float:
+        """Device-wide rate of single-bit LDS atomic ORs (lane ORs/s)."""
+        r = ctypes.c_double(0)
+        self._check(self._lib.pms_lds_rate(self._h, ctypes.byref(r)))
+        return r.value
 
     def serve_stats(self) -> dict:
         s = ServeStats()

@@ -433,4 +433,57 @@ uint64_t test_rate_tests_per_thread(int iters)
     return (uint64_t)iters * (uint64_t)(kCalCand * kCalY);
 }
 
+// LDS calibration: single-bit 32-bit atomic ORs, the tile kernels' mark, at
+// their occupancy (512-thread workgroups, 32 KiB of LDS each, four per CU).
+// Within each half wave the 32 lanes hit 32 different banks. Every index is
+// masked into the array.
+constexpr int kLdsCalWords = 8192;
+constexpr int kLdsCalTPB = 512;
+constexpr int kLdsCalUnroll = 16;
+
+__global__ __launch_bounds__(kLdsCalTPB, kLdsCalTPB / 64) void
+k_lds_rate(int iters, unsigned int *sink)
+{
+    __shared__ unsigned int buf[kLdsCalWords];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < (uint32_t)kLdsCalWords; i += kLdsCalTPB)
+        buf[i] = 0;
+    __syncthreads();
+    uint32_t off = ((tid >> 6) * 1024u + (tid & 63u)) & (kLdsCalWords - 1);
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int k = 0; k < kLdsCalUnroll; k++)
+            atomicOr(&buf[(off + 64u * (uint32_t)k) & (kLdsCalWords - 1)],
+                     1u << ((uint32_t)(it + k) & 31u));
+        off = (off + 1024u) & (kLdsCalWords - 1);
+    }
+    __syncthreads();
+    if (buf[tid] == 0x12345678u)   // never true; keeps the ORs observable
+        atomicAdd(sink, 1u);
+}
+
+hipError_t launch_lds_rate(int grid, int iters, unsigned int *sink,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lds_rate, dim3(grid), dim3(kLdsCalTPB), 0, st, iters,
+                       sink);
+    return hipGetLastError();
+}
+
+int lds_rate_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_lds_rate,
+                                                     kLdsCalTPB, 0) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+uint64_t lds_rate_ors_per_block(int iters)
+{
+    return (uint64_t)iters * kLdsCalUnroll * kLdsCalTPB;
+}
+
 }  // namespace pms

@@ -1094,13 +1094,13 @@ int tiled_blocks_per_cu(bool wide)
 // the marking; then A &= U is written back (U read and cleared in one LDS
 // instruction) and the tile's liveness recorded for the next pass. Tiles
 // are taken in chunks of kBitsetChunk from a counter, so that workgroups
-// stay balanced as tiles die out.
-constexpr int kBitsetChunk = 8;
-
+// stay balanced as tiles die out (the host sizes the chunks so that every
+// workgroup gets several). 256 threads: the 16 words of A per thread stay
+// in registers across the marking without spills.
 template <int TPB>
 __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
                             unsigned long long *A, uint8_t *alive,
-                            unsigned int *next, TileStats *stats)
+                            unsigned int *next, int chunk, TileStats *stats)
 {
     constexpr int kTPB = TPB;
     constexpr int kPer = kMaxWords / TPB;   // words of A per thread
@@ -1117,7 +1117,7 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
     for (int i = tid; i < kMaxWords; i += kTPB)
         sh.U[i] = 0;
     unsigned long long marks = 0, passes = 0;
-    const uint64_t nchunks = (I.ntiles + kBitsetChunk - 1) / kBitsetChunk;
+    const uint64_t nchunks = (I.ntiles + chunk - 1) / (uint64_t)chunk;
     for (;;) {
         __syncthreads();
         if (tid == 0)
@@ -1126,8 +1126,8 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
         const uint64_t ch = uni(s_chunk);
         if (ch >= nchunks)
             break;
-        const uint64_t t1 = min((ch + 1) * kBitsetChunk, I.ntiles);
-        for (uint64_t t = ch * kBitsetChunk; t < t1; t++) {
+        const uint64_t t1 = min((ch + 1) * (uint64_t)chunk, I.ntiles);
+        for (uint64_t t = ch * (uint64_t)chunk; t < t1; t++) {
             if (pass > 0 && alive[t] == 0)
                 continue;
             unsigned long long *Ag = A + t * (uint64_t)W;
@@ -1135,7 +1135,9 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
 #pragma unroll
             for (int k = 0; k < kPer; k++) {
                 const int w = tid + k * kTPB;
-                a[k] = (pass > 0 && w < W) ? Ag[w] : ~0ull;
+                // A is streamed once per pass: non-temporal access
+                a[k] = (pass > 0 && w < W) ? __builtin_nontemporal_load(&Ag[w])
+                                           : ~0ull;
             }
             uint32_t Phi, Plo;
             prefix_planes(t, pl, Phi, Plo);
@@ -1153,7 +1155,7 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
                         &sh.U[pbase ^ wpos((uint32_t)(k * kTPB))], 0ull,
                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     const unsigned long long v = a[k] & u;
-                    Ag[w] = v;
+                    __builtin_nontemporal_store(v, &Ag[w]);
                     nz |= (v != 0);
                 }
             }
@@ -1168,21 +1170,21 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
     }
 }
 
-__global__ __launch_bounds__(kTPBWide, kTPBWide / 64) void
+__global__ __launch_bounds__(kTPB, kTPB / 64) void
 k_bitset_pass(const InstDev *inst, int pass, Tables tb,
               unsigned long long *A, uint8_t *alive, unsigned int *next,
-              TileStats *stats)
+              int chunk, TileStats *stats)
 {
-    bitset_pass<kTPBWide>(inst, pass, tb, A, alive, next, stats);
+    bitset_pass<kTPB>(inst, pass, tb, A, alive, next, chunk, stats);
 }
 
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              unsigned int *next, TileStats *stats, int grid,
-                              hipStream_t st)
+                              unsigned int *next, int chunk, TileStats *stats,
+                              int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPBWide), 0, st,
-                       d_inst, pass, tb, A, alive, next, stats);
+    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                       pass, tb, A, alive, next, chunk, stats);
     return hipGetLastError();
 }
 
@@ -1190,7 +1192,7 @@ int bitset_blocks_per_cu()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bitset_pass,
-                                                     kTPBWide, 0) != hipSuccess ||
+                                                     kTPB, 0) != hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;

@@ -706,14 +706,18 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
                 return rc;
             base = (char *)c->arena.p;
             const int grid = grid_for(c, c->tiled_bpc);
+            // tiles in chunks of up to 8, at least 8 chunks per workgroup
+            const int bgrid = grid_for(c, c->bitset_bpc);
+            const int bchunk = (int)std::max<uint64_t>(
+                1, std::min<uint64_t>(8, ntiles / ((uint64_t)bgrid * 8)));
             for (int pass = 0; pass < n; pass++) {
                 // every pass takes tiles from a counter of its own
                 HIPCHK(c, launch_fill_u64(d_next, 1, 0, st));
                 HIPCHK(c, launch_bitset_pass(d_inst, pass, c->tb,
                                              (unsigned long long *)c->bitset.p,
                                              (uint8_t *)c->alive.p,
-                                             (unsigned int *)d_next, d_stats,
-                                             grid_for(c, c->bitset_bpc), st));
+                                             (unsigned int *)d_next, bchunk,
+                                             d_stats, bgrid, st));
             }
             S.main_launches = n;
             HIPCHK(c, hipEventRecord(c->ev[2], st));

@@ -268,10 +268,12 @@ hipError_t launch_tiled_quorum(const InstDev *d_insts, const WorkItem *d_items,
 int tiled_quorum_blocks_per_cu();
 
 // Memory-heavy bitset path: one pass per string over the whole 4^l space.
+// One string pass of the memory-heavy path; tiles are taken `chunk` at a
+// time from *next (cleared by the caller before the launch).
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              unsigned int *next, TileStats *stats, int grid,
-                              hipStream_t st);
+                              unsigned int *next, int chunk, TileStats *stats,
+                              int grid, hipStream_t st);
 int bitset_blocks_per_cu();
 hipError_t launch_bitset_count(const InstDev *d_inst,
                                const unsigned long long *A,
@@ -297,6 +299,10 @@ int filter_blocks_per_cu();
 // calibration kernel: the filter's Hamming-test mix from registers only
 hipError_t launch_test_rate(int grid, int iters, uint32_t seed,
                             unsigned int *sink, hipStream_t st);
+hipError_t launch_lds_rate(int grid, int iters, unsigned int *sink,
+                           hipStream_t st);
+int lds_rate_blocks_per_cu();
+uint64_t lds_rate_ors_per_block(int iters);
 int test_rate_blocks_per_cu();
 uint64_t test_rate_tests_per_thread(int iters);
 

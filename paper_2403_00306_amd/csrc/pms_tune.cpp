@@ -183,3 +183,31 @@ extern "C" int pms_test_rate(pms_ctx *c, double *tests_per_s)
     *tests_per_s = (double)per_iter * (double)iters / ((double)ms / 1e3);
     return PMS_OK;
 }
+
+extern "C" int pms_lds_rate(pms_ctx *c, double *ors_per_s)
+{
+    if (!c || !ors_per_s)
+        return PMS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = c->alloc(c->aux, 256);
+    if (rc)
+        return rc;
+    const hipStream_t st = c->stream;
+    const int grid = std::max(1, c->n_cu * lds_rate_blocks_per_cu());
+    unsigned int *sink = (unsigned int *)c->aux.p;
+    HIPCHK(c, launch_lds_rate(grid, 16, sink, st));   // warm-up
+    // about 1e11 ORs: a few tens of milliseconds
+    const uint64_t per_iter = (uint64_t)grid * lds_rate_ors_per_block(1);
+    const int iters = (int)std::max<uint64_t>(
+        16, std::min<uint64_t>(1u << 20, 100000000000ull / per_iter));
+    HIPCHK(c, hipEventRecord(c->ev[0], st));
+    HIPCHK(c, launch_lds_rate(grid, iters, sink, st));
+    HIPCHK(c, hipEventRecord(c->ev[1], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[1]));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    if (ms <= 0)
+        return c->fail(PMS_EDEVICE, "lds rate: no elapsed time");
+    *ors_per_s = (double)per_iter * (double)iters / ((double)ms / 1e3);
+    return PMS_OK;
+}

@@ -20,3 +20,13 @@ def test_test_rate_is_physical():
         assert r * 3.75 <= 1.1 * peak, r
     print("tests/s", r1, r2, "fraction of derived peak", r1 * 3.75 / peak,
           flush=True)
+
+
+def test_lds_rate_is_physical():
+    # single-bit LDS atomic ORs: at most one per bank (32) per clock per CU
+    with pms.Context() as c:
+        r = c.lds_rate()
+    peak = 256 * 32 * 2.4e9
+    assert 0 < r <= 1.1 * peak, r
+    print("lds ORs/s", r, "lane ORs per CU clock", r / (256 * 2.4e9),
+          flush=True)
