@@ -364,14 +364,14 @@ def pair_bench(pms, inst, np) -> dict:
                          "frac": ops / (st["ms_main"] / 1000.0) / PEAK_ALU_OPS}}
 
 
-def serve_bench(pms, pmsgen, np, count: int) -> dict:
+def serve_bench(pms, pmsgen, np, count: int, launch_ms: float = 0.0) -> dict:
     """Poisson request stream through the continuous-batching engine:
     first a saturation pass (all requests at t=0) gives the capacity C;
     then an open-loop pass at rate 0.8*C reports p50/p99 latency."""
     reqs = pmsgen.served(seed=11, count=count)
 
     def run(rate):
-        ctx = pms.Context(device=0, serve_slots=64)
+        ctx = pms.Context(device=0, serve_slots=64, serve_launch_ms=launch_ms)
         t_start = ctx.clock_ms()
         tickets = []
         for r in reqs:
@@ -416,6 +416,7 @@ def serve_bench(pms, pmsgen, np, count: int) -> dict:
             "saturation_p50_ms": float(np.percentile(lat_sat, 50)),
             "max_inflight": int(st["max_inflight"]),
             "launches": int(st["launches"]),
+            "launch_ms_target": launch_ms or None,
             "mix_equals_saturated_and_alone": bool(same and alone_ok)}
 
 
@@ -432,6 +433,9 @@ def main():
     ap.add_argument("--no-hard", action="store_true",
                     help="skip the (19,7)/(21,8)/(23,9) leg (~17 s)")
     ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-launch-ms", type=float, default=0.0,
+                    help="device time each serving launch aims at "
+                         "(0: the library default)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: one device copy of this size at the end, to "
@@ -578,7 +582,8 @@ def main():
         log(json.dumps(extra["batched"]))
     if not args.no_serve:
         log("served")
-        extra["served"] = serve_bench(pms, pmsgen, np, args.serve_count)
+        extra["served"] = serve_bench(pms, pmsgen, np, args.serve_count,
+                                      args.serve_launch_ms)
         log(json.dumps(extra["served"]))
     cpu = None
     if not args.no_cpu:

@@ -240,6 +240,8 @@ int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
  * it; the context's engine thread admits queued requests while device
  * memory and slots allow and runs admitted requests' work together, a
  * bounded slice per launch, so requests join and leave between launches.
+ * Two launches are in flight: the next is queued while the current runs,
+ * and finished requests are compacted and copied out beside it.
  * Each launch aims at pms_options.serve_launch_ms of device time (default
  * 16 ms), shared equally by cost among the admitted requests (processor
  * sharing): a small request finishes within a launch or two, a large one in
@@ -333,7 +335,9 @@ int pms_last_stats(const pms_ctx *ctx, pms_stats *out);
 typedef struct {
     uint64_t submitted, completed, launches;
     uint64_t max_inflight;
-    double busy_ms;           /* engine time with work on the device */
+    double busy_ms;           /* kernel time of the engine's launches */
+    uint64_t retries;         /* requests run again because their motifs
+                                 overflowed the output room sized for them */
 } pms_serve_stats;
 
 int pms_serve_stats_get(const pms_ctx *ctx, pms_serve_stats *out);

@@ -72,7 +72,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint64),
-                ("busy_ms", ctypes.c_double)]
+                ("busy_ms", ctypes.c_double), ("retries", ctypes.c_uint64)]
 
 
 _lib = None

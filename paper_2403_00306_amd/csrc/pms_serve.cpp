@@ -7,10 +7,18 @@
 // indexed on the device and then advance together: every launch of the
 // tiled kernel drains a work list that holds a slice of tiles from every
 // admitted request, sized so that one launch is short. Requests that arrive
-// meanwhile join at the next launch; a request whose tiles are all done is
+// meanwhile join at a later launch; a request whose tiles are all done is
 // compacted into its ascending motif set, copied out, and leaves, freeing
 // its slot and memory. No kernel waits on host-written memory: each launch
 // ends when its work list is drained.
+//
+// Two launches are in flight: while launch k runs, the engine keeps
+// admitting requests; shortly before k's predicted end it plans launch k+1
+// (its work list in the other of two buffers) and queues it behind k on the
+// same stream, then waits for k. The requests whose last tiles ran in k are
+// compacted and copied out on a second stream while k+1 runs, so the device
+// does not idle through the host's work between launches, and a request
+// that arrives during a launch still joins the next one.
 #include "pms_host.h"
 
 #include <algorithm>
@@ -27,9 +35,9 @@ namespace pms {
 
 namespace {
 
-// default device time aimed at per launch: every launch ends in a host
-// synchronisation, so longer launches waste less of the GPU between them
-// (at the cost of a longer wait for the smallest requests)
+// default device time aimed at per launch: shorter launches finish the
+// smallest requests sooner, longer ones cost less per launch (a work list
+// copy, a counter fill, a kernel's ramp-up and tail)
 constexpr double kLaunchTargetMs = 16.0;
 constexpr int kMaxOrder = 4096;          // strings per request (serving)
 
@@ -100,6 +108,13 @@ struct Req {
 
 }  // namespace
 
+// One launch of the tile kernel that the engine has queued.
+struct Launch {
+    bool queued = false;
+    std::vector<Req *> last;   // requests whose last tiles are in it
+    double planned = 0;        // its planned work (cost model units)
+};
+
 struct Server {
     pms_ctx *c = nullptr;
     std::thread th;
@@ -118,16 +133,18 @@ struct Server {
     size_t pool_bytes = 0;
     void *ctl_mem = nullptr;   // slots, items, counter, stats
     InstDev *d_slots = nullptr;
-    WorkItem *d_items = nullptr;
-    unsigned int *d_next = nullptr;
+    WorkItem *d_items[2] = {nullptr, nullptr};   // per launch buffer
+    unsigned int *d_next[2] = {nullptr, nullptr};
     TileStats *d_stats = nullptr;
     size_t max_items = 0;
-    WorkItem *h_items = nullptr;     // pinned
+    WorkItem *h_items[2] = {nullptr, nullptr};   // pinned
     InstDev *h_desc = nullptr;       // pinned
     unsigned long long *h_small = nullptr;   // pinned
     int *h_order = nullptr;          // pinned
-    hipStream_t st = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t st = nullptr;        // index kernels and launches
+    hipStream_t st_out = nullptr;    // compaction and copies of results
+    hipEvent_t e0[2] = {nullptr, nullptr}, e1[2] = {nullptr, nullptr};
+    Launch L[2];
     double ops_per_ms = 5.0e9;       // refined from measured launches
     pms_serve_stats stats{};
     std::string err;
@@ -135,6 +152,7 @@ struct Server {
     int start();
     void run();
     int setup(Req *r);
+    int plan_launch(int b, const std::vector<Req *> &act);
     int finalize(std::vector<Req *> &fin);
 };
 
@@ -158,8 +176,9 @@ int Server::start()
     pool.reset(pool_bytes);
     max_items = 1 << 16;
     const size_t o_items = align_up(sizeof(InstDev) * max_slots);
-    const size_t o_next = o_items + align_up(sizeof(WorkItem) * max_items);
-    const size_t o_stats = o_next + 256;
+    const size_t items_bytes = align_up(sizeof(WorkItem) * max_items);
+    const size_t o_next = o_items + 2 * items_bytes;
+    const size_t o_stats = o_next + 2 * 256;
     const size_t ctl = o_stats + align_up(sizeof(TileStats));
     if (hipMalloc(&ctl_mem, ctl) != hipSuccess) {
         (void)hipGetLastError();
@@ -167,10 +186,14 @@ int Server::start()
     }
     c->held += ctl;
     d_slots = (InstDev *)ctl_mem;
-    d_items = (WorkItem *)((char *)ctl_mem + o_items);
-    d_next = (unsigned int *)((char *)ctl_mem + o_next);
+    for (int b = 0; b < 2; b++) {
+        d_items[b] = (WorkItem *)((char *)ctl_mem + o_items + b * items_bytes);
+        d_next[b] = (unsigned int *)((char *)ctl_mem + o_next + b * 256);
+    }
     d_stats = (TileStats *)((char *)ctl_mem + o_stats);
-    if (hipHostMalloc((void **)&h_items, sizeof(WorkItem) * max_items) !=
+    if (hipHostMalloc((void **)&h_items[0], sizeof(WorkItem) * max_items) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&h_items[1], sizeof(WorkItem) * max_items) !=
             hipSuccess ||
         hipHostMalloc((void **)&h_desc, sizeof(InstDev) * max_slots) !=
             hipSuccess ||
@@ -179,9 +202,15 @@ int Server::start()
         hipHostMalloc((void **)&h_order, 4 * kMaxOrder * (size_t)max_slots) !=
             hipSuccess)
         return c->fail(PMS_EDEVICE, "serving pinned staging failed");
+    // both streams at the default priority
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return c->fail(PMS_EDEVICE, "serving stream/events failed");
+        hipStreamCreateWithFlags(&st_out, hipStreamNonBlocking) !=
+            hipSuccess)
+        return c->fail(PMS_EDEVICE, "serving streams failed");
+    for (int b = 0; b < 2; b++)
+        if (hipEventCreate(&e0[b]) != hipSuccess ||
+            hipEventCreate(&e1[b]) != hipSuccess)
+            return c->fail(PMS_EDEVICE, "serving events failed");
     for (int i = max_slots - 1; i >= 0; i--)
         free_slots.push_back(i);
     th = std::thread([this] { run(); });
@@ -218,6 +247,8 @@ int Server::setup(Req *r)
 }
 
 // Compact finished requests and copy their results out (engine thread).
+// Their last launch has completed; the work runs on st_out, beside the
+// launch that is running on st.
 int Server::finalize(std::vector<Req *> &fin)
 {
     for (size_t i = 0; i < fin.size(); i++) {
@@ -226,20 +257,19 @@ int Server::finalize(std::vector<Req *> &fin)
         uint64_t *tile_pos = (uint64_t *)(base + r->lay.tile_pos);
         uint64_t *out = (uint64_t *)(base + r->lay.out);
         if (launch_scan_u32(r->desc.tile_cnt, r->ntiles, tile_pos,
-                            base + r->lay.scan, st) != hipSuccess ||
+                            base + r->lay.scan, st_out) != hipSuccess ||
             launch_gather(r->desc.tile_cnt, r->desc.tile_heap_off, tile_pos,
                           r->desc.heap, r->ntiles, out, r->heap_cap,
-                          r->heap_cap, st) !=
-                hipSuccess ||
+                          r->heap_cap, st_out) != hipSuccess ||
             hipMemcpyAsync(h_small + 3 * i, tile_pos + r->ntiles, 8,
-                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+                           hipMemcpyDeviceToHost, st_out) != hipSuccess ||
             hipMemcpyAsync(h_small + 3 * i + 1, r->desc.heap_top, 8,
-                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+                           hipMemcpyDeviceToHost, st_out) != hipSuccess ||
             hipMemcpyAsync(h_small + 3 * i + 2, r->desc.bad, 8,
-                           hipMemcpyDeviceToHost, st) != hipSuccess)
+                           hipMemcpyDeviceToHost, st_out) != hipSuccess)
             return PMS_EDEVICE;
     }
-    if (hipStreamSynchronize(st) != hipSuccess)
+    if (hipStreamSynchronize(st_out) != hipSuccess)
         return PMS_EDEVICE;
     for (size_t i = 0; i < fin.size(); i++) {
         Req *r = fin[i];
@@ -260,12 +290,77 @@ int Server::finalize(std::vector<Req *> &fin)
         r->result.resize(total);
         if (total &&
             hipMemcpyAsync(r->result.data(), base + r->lay.out, total * 8,
-                           hipMemcpyDeviceToHost, st) != hipSuccess)
+                           hipMemcpyDeviceToHost, st_out) != hipSuccess)
             return PMS_EDEVICE;
         r->status = PMS_OK;
     }
-    if (hipStreamSynchronize(st) != hipSuccess)
+    if (hipStreamSynchronize(st_out) != hipSuccess)
         return PMS_EDEVICE;
+    return PMS_OK;
+}
+
+// Plan launch buffer b: a slice of every admitted request's remaining
+// tiles, sized by processor sharing, queued on st behind whatever runs.
+// Requests whose last tiles go into it are noted in L[b].last.
+int Server::plan_launch(int b, const std::vector<Req *> &act)
+{
+    Launch &Lb = L[b];
+    Lb.last.clear();
+    Lb.planned = 0;
+    Lb.queued = false;
+    const double budget = launch_ms * ops_per_ms;
+    size_t nleft = 0;
+    for (Req *r : act)
+        nleft += r->next_tile < r->ntiles;
+    if (nleft == 0)
+        return PMS_OK;
+    const double share = budget / (double)nleft;
+    size_t ni = 0;
+    double planned_wide = 0;
+    WorkItem *hi = h_items[b];
+    for (Req *r : act) {
+        const uint64_t left = r->ntiles - r->next_tile;
+        if (!left)
+            continue;
+        uint64_t q = (uint64_t)std::max(1.0, share / r->cost_per_tile);
+        q = std::min(q, left);
+        const uint64_t chunk =
+            std::max<uint64_t>(1, std::min<uint64_t>(16, q / 64));
+        uint64_t t = r->next_tile;
+        const uint64_t end = r->next_tile + q;
+        while (t < end && ni < max_items) {
+            WorkItem w;
+            w.inst = r->slot;
+            w.pad = 0;
+            w.t0 = t;
+            w.t1 = std::min(t + chunk, end);
+            hi[ni++] = w;
+            t = w.t1;
+        }
+        const uint64_t took = t - r->next_tile;
+        r->next_tile = t;
+        Lb.planned += (double)took * r->cost_per_tile;
+        if (r->s >= kWideMinSuffix)
+            planned_wide += (double)took * r->cost_per_tile;
+        if (r->next_tile >= r->ntiles)
+            Lb.last.push_back(r);
+    }
+    if (ni == 0)
+        return PMS_OK;
+    // the 512-thread tile kernel when most of this launch's work is in
+    // tiles of at least 4^8 codes
+    const bool wide = pick_wide(c, planned_wide >= 0.5 * Lb.planned);
+    const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
+    if (hipMemcpyAsync(d_items[b], hi, sizeof(WorkItem) * ni,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_fill_u32(d_next[b], 1, 0, st) != hipSuccess ||
+        hipEventRecord(e0[b], st) != hipSuccess ||
+        launch_tiled(d_slots, d_items[b], (int)ni, 0, d_next[b], c->tb,
+                     nullptr, std::max(1, c->n_cu * tbpc), st,
+                     wide) != hipSuccess ||
+        hipEventRecord(e1[b], st) != hipSuccess)
+        return PMS_EDEVICE;
+    Lb.queued = true;
     return PMS_OK;
 }
 
@@ -273,6 +368,11 @@ void Server::run()
 {
     hipSetDevice(c->device);
     std::unique_lock<std::mutex> lk(mu);
+    int b = 0;   // launch buffer to plan next; b ^ 1 may be in flight
+    // predicted end of the launch in flight (steady clock, ms): the next
+    // launch is queued shortly before it, so that requests arriving until
+    // then still join the next launch
+    double inflight_end = 0;
     for (;;) {
         // ---- admission: first come first served, by slot and memory ----
         std::vector<Req *> fresh;
@@ -300,7 +400,8 @@ void Server::run()
             fresh.push_back(r);
             active.push_back(r);
         }
-        if (active.empty()) {
+        const int pb = b ^ 1;
+        if (active.empty() && !L[pb].queued) {
             if (stop)
                 break;
             cv.wait(lk);
@@ -316,84 +417,84 @@ void Server::run()
             if (rc == PMS_OK)
                 rc = setup(r);
 
-        // ---- one launch: a slice of every admitted request's tiles ------
-        const double t0 = now_ms();
-        const double budget = launch_ms * ops_per_ms;
-        const double share = budget / (double)act.size();
-        size_t ni = 0;
-        double planned = 0, planned_wide = 0;
-        std::vector<uint64_t> took(act.size(), 0);
-        for (size_t a = 0; a < act.size() && rc == PMS_OK; a++) {
-            Req *r = act[a];
-            const uint64_t left = r->ntiles - r->next_tile;
-            if (!left)
+        // ---- not yet time to queue the next launch: admit more ----------
+        if (rc == PMS_OK && L[pb].queued) {
+            const double margin = std::max(0.5, 0.25 * launch_ms);
+            const hipError_t q = hipEventQuery(e1[pb]);
+            (void)hipGetLastError();   // "not ready" is no error here
+            const double wait = inflight_end - margin - now_ms();
+            if (q == hipErrorNotReady && wait > 0.05) {
+                lk.lock();
+                cv.wait_for(lk, std::chrono::microseconds(
+                                    (long long)(std::min(wait, 0.25) * 1e3)));
                 continue;
-            uint64_t q = (uint64_t)std::max(1.0, share / r->cost_per_tile);
-            q = std::min(q, left);
-            const uint64_t chunk =
-                std::max<uint64_t>(1, std::min<uint64_t>(16, q / 64));
-            uint64_t t = r->next_tile;
-            const uint64_t end = r->next_tile + q;
-            while (t < end && ni < max_items) {
-                WorkItem w;
-                w.inst = r->slot;
-                w.pad = 0;
-                w.t0 = t;
-                w.t1 = std::min(t + chunk, end);
-                h_items[ni++] = w;
-                t = w.t1;
             }
-            took[a] = t - r->next_tile;
-            planned += (double)took[a] * r->cost_per_tile;
-            if (r->s >= kWideMinSuffix)
-                planned_wide += (double)took[a] * r->cost_per_tile;
         }
-        if (rc == PMS_OK && ni > 0) {
-            // the 512-thread tile kernel when most of this launch's work is
-            // in tiles of at least 4^8 codes
-            const bool wide = pick_wide(c, planned_wide >= 0.5 * planned);
-            const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
-            if (hipMemcpyAsync(d_items, h_items, sizeof(WorkItem) * ni,
-                               hipMemcpyHostToDevice, st) != hipSuccess ||
-                launch_fill_u32(d_next, 1, 0, st) != hipSuccess ||
-                hipEventRecord(e0, st) != hipSuccess ||
-                launch_tiled(d_slots, d_items, (int)ni, 0, d_next, c->tb,
-                             nullptr, std::max(1, c->n_cu * tbpc), st,
-                             wide) != hipSuccess ||
-                hipEventRecord(e1, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess)
-                rc = PMS_EDEVICE;
-            float ms = 0;
-            if (rc == PMS_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
-                ms > 0.05)
-                ops_per_ms = 0.7 * ops_per_ms + 0.3 * (planned / ms);
-        }
+
+        // ---- queue launch b behind the one in flight --------------------
+        const double t_queue = now_ms();
+        if (rc == PMS_OK)
+            rc = plan_launch(b, act);
+        double b_end = 0;
+        if (L[b].queued)
+            b_end = (L[pb].queued ? std::max(t_queue, inflight_end)
+                                  : t_queue) +
+                    L[b].planned / ops_per_ms;
+
+        // ---- wait for the launch in flight, finish its requests ---------
         std::vector<Req *> fin;
-        for (size_t a = 0; a < act.size(); a++) {
-            act[a]->next_tile += took[a];
-            if (act[a]->next_tile >= act[a]->ntiles)
-                fin.push_back(act[a]);
+        double kms = 0;
+        if (rc == PMS_OK && L[pb].queued) {
+            if (hipEventSynchronize(e1[pb]) != hipSuccess) {
+                rc = PMS_EDEVICE;
+            } else {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e0[pb], e1[pb]) == hipSuccess) {
+                    kms = ms;
+                    if (ms > 0.05)
+                        ops_per_ms = 0.7 * ops_per_ms +
+                                     0.3 * (L[pb].planned / ms);
+                }
+                fin = L[pb].last;
+                if (!fin.empty())
+                    rc = finalize(fin);
+            }
+            L[pb].queued = false;
+            L[pb].last.clear();
+            // launch b started when pb ended
+            if (L[b].queued)
+                b_end = now_ms() + L[b].planned / ops_per_ms;
+        } else if (rc == PMS_OK && !L[b].queued && !fresh.empty()) {
+            // nothing to launch yet: let the new requests' index kernels
+            // finish before they are planned
+            if (hipStreamSynchronize(st) != hipSuccess)
+                rc = PMS_EDEVICE;
         }
-        if (rc == PMS_OK && !fin.empty())
-            rc = finalize(fin);
-        const double t1 = now_ms();
+        inflight_end = b_end;
 
         lk.lock();
-        stats.launches++;
-        stats.busy_ms += t1 - t0;
+        if (kms > 0) {
+            stats.launches++;
+            stats.busy_ms += kms;
+        }
         if (rc != PMS_OK) {
             // device failure: fail every admitted request
             err = "serving engine: HIP error";
+            hipStreamSynchronize(st);
+            hipStreamSynchronize(st_out);
+            L[0] = Launch();
+            L[1] = Launch();
             fin = active;
             for (Req *r : fin)
                 r->status = PMS_EDEVICE;
         }
         for (Req *r : fin) {
+            pool.give(r->pool_off, r->pool_bytes);
+            free_slots.push_back(r->slot);
+            active.erase(std::find(active.begin(), active.end(), r));
             if (r->status == PMS_PENDING) {
-                // overflowed heap: give the memory back and queue again
-                pool.give(r->pool_off, r->pool_bytes);
-                free_slots.push_back(r->slot);
-                active.erase(std::find(active.begin(), active.end(), r));
+                // overflowed heap: queue again, at the head, with room
+                stats.retries++;
                 r->lay = layout_instance(r->n, r->m, r->l, r->ntiles,
                                          r->heap_cap, true, true, true);
                 r->pool_bytes = r->lay.total;
@@ -403,15 +504,13 @@ void Server::run()
                 queue.push_front(r);
                 continue;
             }
-            pool.give(r->pool_off, r->pool_bytes);
-            free_slots.push_back(r->slot);
-            active.erase(std::find(active.begin(), active.end(), r));
             r->state = 2;
             r->t_done = now_ms();
             stats.completed++;
         }
         if (!fin.empty())
             done_cv.notify_all();
+        b ^= 1;
     }
 }
 
@@ -435,26 +534,33 @@ void serve_shutdown(pms_ctx *c)
         s->th.join();
     if (s->st)
         hipStreamSynchronize(s->st);
+    if (s->st_out)
+        hipStreamSynchronize(s->st_out);
     if (s->pool_mem) {
         hipFree(s->pool_mem);
         c->held -= s->pool_bytes;
     }
     if (s->ctl_mem)
         hipFree(s->ctl_mem);
-    if (s->h_items)
-        hipHostFree(s->h_items);
+    for (int b = 0; b < 2; b++)
+        if (s->h_items[b])
+            hipHostFree(s->h_items[b]);
     if (s->h_desc)
         hipHostFree(s->h_desc);
     if (s->h_small)
         hipHostFree(s->h_small);
     if (s->h_order)
         hipHostFree(s->h_order);
-    if (s->e0)
-        hipEventDestroy(s->e0);
-    if (s->e1)
-        hipEventDestroy(s->e1);
+    for (int b = 0; b < 2; b++) {
+        if (s->e0[b])
+            hipEventDestroy(s->e0[b]);
+        if (s->e1[b])
+            hipEventDestroy(s->e1[b]);
+    }
     if (s->st)
         hipStreamDestroy(s->st);
+    if (s->st_out)
+        hipStreamDestroy(s->st_out);
     delete s;
     c->srv = nullptr;
 }

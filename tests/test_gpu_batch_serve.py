@@ -65,6 +65,43 @@ def test_batch_graph_replays_with_eager_work_between():
             assert c.stats()["graph_replayed"] == 0
 
 
+def test_batch_graph_replay_with_new_contents():
+    # the replay key is the batch shape, not the bytes: a second draw of
+    # the same (n, m, l, d) shapes must replay the graph and still give the
+    # second draw's sets (the input copy and the index are inside the graph)
+    shapes = [(x.n, x.m, x.l, x.d) for x in
+              mixed_instances(61, 12, [(9, 2), (11, 3), (13, 4)], (4, 12),
+                              (60, 250))]
+    first = [pmsgen.planted(100 + i, *sh) for i, sh in enumerate(shapes)]
+    second = [pmsgen.planted(900 + i, *sh) for i, sh in enumerate(shapes)]
+    with pms.Context() as c:
+        c.solve_batch(first)
+        assert c.stats()["graph_replayed"] == 0
+        for rep, insts in enumerate((second, first, second)):
+            got = c.solve_batch(insts)
+            assert c.stats()["graph_replayed"] == 1, rep
+            for i, x in enumerate(insts):
+                np.testing.assert_array_equal(
+                    got[i], oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0],
+                    err_msg="replay %d inst %d" % (rep, i))
+
+
+def test_plain_solve_counts_each_retry_once():
+    # two-letter strings at (10,3): about 1.1e5 motifs, above the first
+    # output estimate (2^16 codes); the first solve retries once, a repeat
+    # of the shape starts with the room it needed
+    rng = random.Random(2)
+    n, m, l, d = 3, 200, 10, 3
+    s = bytes(rng.choice(b"AT") for _ in range(n * m))
+    want = oracle.o1(s, n, m, l, d)[0]
+    with pms.Context(path=pms.PATH_TILED) as c:
+        assert len(want) > 1 << 16
+        np.testing.assert_array_equal(c.solve(s, n, m, l, d), want)
+        assert c.stats()["retries"] == 1
+        np.testing.assert_array_equal(c.solve(s, n, m, l, d), want)
+        assert c.stats()["retries"] == 0
+
+
 @pytest.mark.parametrize("threads", [0, 256, 512])
 def test_batch_tile_kernel_sizes(threads):
     # (13,4) and (14,4) take tiles of 4^8 and 4^9 codes, where the automatic
@@ -132,6 +169,29 @@ def test_served_tile_kernel_sizes(threads):
         np.testing.assert_array_equal(
             res[i], oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0],
             err_msg="request %d" % i)
+
+
+def test_served_output_overflow_retries():
+    # two-letter strings overflow the output room a request is first given
+    # (about 6e4 motifs): the engine runs such a request again with room,
+    # and the results still match the oracle and the same instance alone
+    rng = random.Random(2)
+    n, m, l, d = 3, 200, 9, 3
+    items = [bytes(rng.choice(b"AT") for _ in range(n * m)) for _ in range(3)]
+    small = mixed_instances(47, 6, [(9, 2), (11, 3)], (4, 10), (60, 200))
+    with pms.Context(serve_slots=4) as c:
+        tickets = [c.submit(x, n, m, l, d) for x in items]
+        tickets += [c.submit(x.seqs, x.n, x.m, x.l, x.d) for x in small]
+        res = [c.wait(t, 60000) for t in tickets]
+        st = c.serve_stats()
+        for t in tickets:
+            c.release(t)
+    assert st["retries"] >= 1
+    for i, x in enumerate(items):
+        np.testing.assert_array_equal(res[i], oracle.o1(x, n, m, l, d)[0])
+    for i, x in enumerate(small):
+        np.testing.assert_array_equal(
+            res[len(items) + i], oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0])
 
 
 def test_served_launch_size():
