@@ -16,6 +16,13 @@ Usage (from the repository root, after the three runs):
   python3 -m paper_2403_00306_amd.profile_tools --name NAME \\
       --stats DIR/..._kernel_stats.csv --fetch DIR/..._counter_collection.csv \\
       --write DIR/..._counter_collection.csv --copy-bytes N --command "..."
+
+and, for SQ counter passes (--pmc runs of up to 8 SQ counters each):
+  python3 -m paper_2403_00306_amd.profile_tools counters --name NAME \\
+      --stats DIR/..._kernel_stats.csv --csv PASS1.csv [PASS2.csv ...] \\
+      --kernels k_tiled_512 [...] --command "..."
+which writes profiles/<name>_counters.md: per-dispatch averages of every
+counter and the derived issue and LDS figures, with the source hash.
 """
 from __future__ import annotations
 
@@ -30,6 +37,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.hip",
+                  "k_lds_rate": "csrc/k_filter.hip",
                   "k_tiled_512": "csrc/k_tiles.hip",
                   "k_tiled_quorum": "csrc/k_tiles.hip",
                   "k_alpha_filter": "csrc/k_alpha.hip",
@@ -135,5 +143,77 @@ def main():
               indent=1)
 
 
+# gfx950: 256 CUs at up to 2.4 GHz; SQ cycle counters count quad-cycles
+CUS = 256
+CLOCK_HZ = 2.4e9
+
+
+def main_counters(argv):
+    ap = argparse.ArgumentParser(prog="profile_tools counters")
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--csv", nargs="+", required=True)
+    ap.add_argument("--kernels", nargs="+", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    a = ap.parse_args(argv)
+    avg_ns = {short(r["Name"]): float(r["AverageNs"])
+              for r in csv.DictReader(open(a.stats))}
+    vals = collections.defaultdict(dict)
+    for path in a.csv:
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            per[short(r["Kernel_Name"])][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+        for k, cs in per.items():
+            for cname, v in cs.items():
+                vals[k][cname] = sum(v) / len(v)
+    lines = ["# SQ counters per dispatch: %s" % a.name, "",
+             "rocprofv3 --pmc passes (at most 8 SQ counters each) of:", "",
+             "    " + a.command, "",
+             "Kernel durations from the --kernel-trace --stats run of the "
+             "same command. Derived figures assume %d CUs at %.1f GHz; "
+             "SQ_WAVE_CYCLES and SQ_WAIT_* count quad-cycles; one wave64 "
+             "VALU instruction per CU clock is the issue peak (4 SIMDs, "
+             "4 clocks each), one SALU instruction per CU clock likewise."
+             % (CUS, CLOCK_HZ / 1e9), ""]
+    for k in a.kernels:
+        v = vals.get(k, {})
+        src = source_hash(k) if k in KERNEL_SOURCES else "-"
+        ns = avg_ns.get(k)
+        lines += ["## %s (source %s)" % (k, src), "",
+                  "| counter | per dispatch |", "|---|---:|"]
+        for cname in sorted(v):
+            lines.append("| %s | %.4g |" % (cname, v[cname]))
+        lines.append("")
+        if ns:
+            cyc = ns * 1e-9 * CLOCK_HZ * CUS      # CU clocks in the dispatch
+            lines += ["average duration %.1f us, %.4g CU clocks" %
+                      (ns / 1e3, cyc), ""]
+            der = []
+            for cname, label in (("SQ_INSTS_VALU", "VALU instructions per CU clock"),
+                                 ("SQ_INSTS_SALU", "SALU instructions per CU clock"),
+                                 ("SQ_INSTS_LDS", "LDS instructions per CU clock")):
+                if cname in v:
+                    der.append("| %s | %.3f |" % (label, v[cname] / cyc))
+            if "SQ_LDS_IDX_ACTIVE" in v:
+                der.append("| LDS active share of CU clocks | %.3f |" %
+                           (v["SQ_LDS_IDX_ACTIVE"] / cyc))
+            if "SQ_LDS_BANK_CONFLICT" in v and v.get("SQ_LDS_IDX_ACTIVE"):
+                der.append("| bank-conflict share of LDS active | %.3f |" %
+                           (v["SQ_LDS_BANK_CONFLICT"] / v["SQ_LDS_IDX_ACTIVE"]))
+            if v.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_ANY" in v:
+                der.append("| waiting share of wave lifetime | %.3f |" %
+                           (v["SQ_WAIT_INST_ANY"] / v["SQ_WAVE_CYCLES"]))
+            if der:
+                lines += ["| derived | value |", "|---|---:|"] + der + [""]
+    open(os.path.join(a.out, "%s_counters.md" % a.name), "w").write(
+        "\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    main()
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        main_counters(sys.argv[2:])
+    else:
+        main()
