@@ -235,10 +235,12 @@ def main_served(upto_l=17):
     _append_sets(path, header, [(i, reqs[i].inst) for i in sel])
 
 
-# Harder instances (Table 3.3's (19,7), (21,8), (23,9) at n = 20, m = 600,
+# Harder instances (Table 3.3's (19,7) and (21,8) at n = 20, m = 600,
 # seed 1): the motifs O1 derives from a few reference l-mers of s_1 (the
 # plant's offset and seeded others). Each is a subset of the whole set.
-HARD = [(19, 7, 3), (21, 8, 3), (23, 9, 1)]
+# (O1 gives one thread per reference, so each takes minutes at (19,7) and
+# a quarter of an hour at (21,8); a (23,9) reference would take hours.)
+HARD = [(19, 7, 3), (21, 8, 3)]
 
 
 def main_hard():

@@ -1,12 +1,20 @@
 """GPU: the harder instances of the thesis's Table 3.3, (19,7), (21,8) and
 (23,9) with n = 20, m = 600, on the tiled path.
 
-The oracle cannot recompute these sets whole (one reference's sphere at
-(21,8) is 1.6e9 candidates), so: at (19,7) the tiled path must equal the
-sample-driven filter path (a different algorithm) code for code; at every
-size each reported code is checked against every string by the oracle, one
-code at a time, and the planted motif must be reported.
+The oracle cannot recompute these sets whole in a test (one reference's
+sphere at (21,8) is 1.6e9 candidates), so: at (19,7) the tiled path must
+equal the sample-driven filter path (a different algorithm) code for code;
+at every size each reported code is checked against every string by the
+oracle's direct check (Definition 5), one code at a time, and the planted
+motif must be reported. Completeness: tests/golden/make_golden.py stored,
+from the oracle, the motifs derived from single reference l-mers of s_1
+(the plant's offset and two seeded others) at (19,7) and (21,8); each such
+subset must lie inside the GPU's set, and at (19,7) the filter path's
+canonical Hamming-test count of each of those references must equal the
+oracle's.
 """
+import hashlib
+import os
 import sys
 
 import pytest
@@ -40,6 +48,35 @@ def check(inst, got):
     assert code_of(inst.motif) in set(int(v) for v in got)
 
 
+def stored_refs(l, d):
+    """(offset j, canonical count of j, codes derived from j) per stored
+    reference of the (l,d) instance."""
+    out = []
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "hard_refs_seed1.txt")
+    inst = pmsgen.planted(1, 20, 600, l, d)
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        t = line.split()
+        if (int(t[0]), int(t[1])) != (l, d):
+            continue
+        assert t[3] == hashlib.sha256(inst.seqs).hexdigest()
+        codes = [] if t[6] == "none" else [int(x) for x in t[6].split(",")]
+        assert len(codes) == int(t[5])
+        out.append((int(t[2]), int(t[4]), codes))
+    return out
+
+
+def check_refs(l, d, got):
+    refs = stored_refs(l, d)
+    assert len(refs) == 3, "stored references of (%d,%d)" % (l, d)
+    have = set(int(v) for v in got)
+    for j, _, codes in refs:
+        assert set(codes) <= have, (l, d, j)
+    return refs
+
+
 def test_hard_19_7_paths_agree():
     inst = pmsgen.planted(1, 20, 600, 19, 7)
     say("hard (19,7) tiled")
@@ -48,8 +85,11 @@ def test_hard_19_7_paths_agree():
     say("hard (19,7) filter")
     with pms.Context(path=pms.PATH_FILTER) as c:
         filt = c.solve(inst.seqs, 20, 600, 19, 7)
+        per = c.hcanon_per_ref(600 - 19 + 1)
     assert list(tiled) == list(filt)
     check(inst, tiled)
+    for j, h, _ in check_refs(19, 7, tiled):
+        assert int(per[j]) == h, j
 
 
 def test_hard_21_8():
@@ -59,6 +99,7 @@ def test_hard_21_8():
         got = c.solve(inst.seqs, 20, 600, 21, 8)
         assert c.stats()["tiles"] == 4 ** 12
     check(inst, got)
+    check_refs(21, 8, got)
 
 
 def test_hard_23_9():
