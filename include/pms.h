@@ -100,6 +100,13 @@ typedef struct {
                                  less of the GPU on the host work between
                                  launches (more capacity, lower p99). The
                                  results do not depend on it. */
+    int pair_partner;         /* PMS_PATH_PAIR: 0 = for every l-mer x of
+                                 s_1 the string whose nearest l-mer is
+                                 farthest from x (TraverStringRef's string
+                                 reordering, Sec. 3.2.3: smaller pair
+                                 intersections); 1 = s_2 for every x
+                                 (Observation 3.3 as stated). The result
+                                 does not depend on it. */
 } pms_options;
 
 /* Fill *opt with the defaults above (device 0, auto path). */

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("tune_cache", ctypes.c_char_p),
                 ("serve_slots", ctypes.c_int), ("serve_queue", ctypes.c_int),
                 ("tile_threads", ctypes.c_int),
-                ("serve_launch_ms", ctypes.c_double)]
+                ("serve_launch_ms", ctypes.c_double),
+                ("pair_partner", ctypes.c_int)]
 
 
 class CInstance(ctypes.Structure):
@@ -172,7 +173,8 @@ class Context:
     def __init__(self, device: int = 0, path: int = PATH_AUTO,
                  mem_budget_bytes: int = 0, tune_cache: str | None = None,
                  serve_slots: int = 0, serve_queue: int = 0,
-                 tile_threads: int = 0, serve_launch_ms: float = 0.0):
+                 tile_threads: int = 0, serve_launch_ms: float = 0.0,
+                 pair_partner: int = 0):
         self._lib = load_library()
         opt = Options()
         self._lib.pms_default_options(ctypes.byref(opt))
@@ -184,6 +186,7 @@ class Context:
         opt.serve_queue = serve_queue
         opt.tile_threads = tile_threads
         opt.serve_launch_ms = serve_launch_ms
+        opt.pair_partner = pair_partner
         h = ctypes.c_void_p()
         rc = self._lib.pms_create(ctypes.byref(h), ctypes.byref(opt))
         if rc != PMS_OK:

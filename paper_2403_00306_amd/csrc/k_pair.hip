@@ -1,7 +1,11 @@
 // k_pair.hip -- pair-based candidates (Observation 3.3 with q = n).
 //
-// A motif M has an l-mer x in s_1 and an l-mer y in s_2 within distance d,
-// so d_H(x,y) <= 2d and M is in B(x,d) ∩ B(y,d). The candidates of a pair are
+// A motif M has an l-mer x in s_1 and an l-mer y in any other string s_j
+// within distance d, so d_H(x,y) <= 2d and M is in B(x,d) ∩ B(y,d). The
+// string j may be chosen per x (Observation 3.3 needs only that it is
+// fixed before M is known): TraverStringRef takes for every x the string
+// whose nearest l-mer is farthest from x, since the intersections shrink as
+// d_H(x,y) grows (Sec. 3.2.3, string reordering); s_2 is the plain choice. The candidates of a pair are
 // enumerated directly: on the D positions where x and y differ, M takes x's
 // letter (a of them), y's letter (b) or one of the 2 other letters (c); on
 // the l-D positions where they agree it changes e of them (3 letters each);
@@ -9,16 +13,56 @@
 // the intersection is unranked on the device into such a tuple (a,b,c,e),
 // the colouring of the differing positions, the other-letter bits, the set
 // of changed agreeing positions and their letters. Each candidate already
-// has d-neighbours in s_1 and s_2; it is tested against s_3..s_n in order
-// with the XOR/popcount Hamming form of Sec. 3.3.1 and early exit. A motif
-// reached from several pairs is reported once per pair; the caller sorts
-// and drops repeats.
+// has d-neighbours in s_1 and s_j; it is tested against the other strings
+// in input order with the XOR/popcount Hamming form of Sec. 3.3.1 and early
+// exit. A motif reached from several pairs is reported once per pair; the
+// caller sorts and drops repeats.
 #include "pms_internal.h"
 
 namespace pms {
 
 constexpr int kPairPer = 4;                    // candidates per thread
 constexpr int kPairChunk = kTPB * kPairPer;    // candidates per work item
+
+// One workgroup per l-mer x of s_1: each wave takes strings 1, 1+kWaves,
+// ...; the wave's minimum distance to a string comes from a wave
+// reduction; the string with the largest minimum (lowest index on ties)
+// is x's partner.
+__global__ __launch_bounds__(kTPB) void
+k_pair_partner(const uint2 *planes, int n, int L, uint32_t *partner)
+{
+    __shared__ uint32_t best[kWaves];
+    const int x = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint2 xv = planes[x];
+    uint32_t key = 0;   // (min distance << 24) | (2^24 - 1 - j): max wins
+    for (int j = 1 + wid; j < n; j += kWaves) {
+        const uint2 *row = planes + (size_t)j * L;
+        uint32_t md = 255;
+        for (int k = lane; k < L; k += 64)
+            md = min(md, (uint32_t)__popc((xv.x ^ row[k].x) | (xv.y ^ row[k].y)));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            md = min(md, (uint32_t)__shfl_xor((int)md, o, 64));
+        key = max(key, (md << 24) | (0xFFFFFFu - (uint32_t)j));
+    }
+    if (lane == 0)
+        best[wid] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t k = 0;
+        for (int w = 0; w < kWaves; w++)
+            k = max(k, best[w]);
+        partner[x] = 0xFFFFFFu - (k & 0xFFFFFFu);
+    }
+}
+
+hipError_t launch_pair_partner(const uint2 *planes, int n, int L,
+                               uint32_t *partner, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_partner, dim3(L), dim3(kTPB), 0, st, planes, n,
+                       L, partner);
+    return hipGetLastError();
+}
 
 __global__ __launch_bounds__(kTPB) void
 k_pair_list(PairJob J)
@@ -28,7 +72,8 @@ k_pair_list(PairJob J)
     if (g >= L * L)
         return;
     const uint32_t j = (uint32_t)(g / L), k = (uint32_t)(g % L);
-    const uint2 x = J.planes[j], y = J.planes[L + k];      // s_1, s_2
+    const uint2 x = J.planes[j];                               // s_1
+    const uint2 y = J.planes[(uint64_t)J.partner[j] * L + k];  // its partner
     const int D = __popc((x.x ^ y.x) | (x.y ^ y.y));
     if (D > 2 * J.d)
         return;
@@ -132,14 +177,14 @@ wave_slot(bool keep, unsigned long long *count, unsigned long long &below)
     return base;
 }
 
-// Survivors of string i: to the next queue, or (after the last string) as
+// Survivors of a stage: to the next queue, or (after the last stage) as
 // codes to the heap.
-__device__ __forceinline__ void emit(const PairJob &J, int i,
+__device__ __forceinline__ void emit(const PairJob &J, bool last,
                                      const uint32_t *ch, const uint32_t *cl,
-                                     const bool *live, uint2 *qout,
+                                     const bool *live, const uint32_t *prt,
+                                     uint2 *qout, uint16_t *qpout,
                                      unsigned long long *qcount)
 {
-    const bool last = i >= J.n - 1;
 #pragma unroll
     for (int u = 0; u < kPairPer; u++) {
         unsigned long long below = 0;
@@ -157,6 +202,7 @@ __device__ __forceinline__ void emit(const PairJob &J, int i,
                 J.heap[at] = code;
         } else if (at < J.qcap) {
             qout[at] = make_uint2(ch[u], cl[u]);
+            qpout[at] = (uint16_t)prt[u];
         } else {
             atomicOr(J.overflow, 1u);
         }
@@ -201,7 +247,9 @@ k_pair_filter(PairJob J, unsigned long long it1, unsigned long long npairs)
             break;
         const unsigned long long pi = s_pair;
         const uint2 pr = J.pairs[pi];
-        const uint2 x = J.planes[pr.x], y = J.planes[(uint64_t)J.L + pr.y];
+        const uint32_t prt = J.partner[pr.x];
+        const uint2 x = J.planes[pr.x];
+        const uint2 y = J.planes[(uint64_t)prt * J.L + pr.y];
         const uint32_t dm = (x.x ^ y.x) | (x.y ^ y.y);
         const int D = __popc(dm);
         const uint64_t nD = J.nD[D];
@@ -296,10 +344,17 @@ k_pair_filter(PairJob J, unsigned long long it1, unsigned long long npairs)
                 set_letter(ch[u], cl[u], p, xv ^ w);
             }
         }
-        // s_3 here; the later strings run on the compacted queue
+        // the first string other than s_1 and the partner here; the later
+        // ones run on the compacted queue
+        const int first = prt == 1u ? 2 : 1;
+        uint32_t prts[kPairPer];
+#pragma unroll
+        for (int u = 0; u < kPairPer; u++)
+            prts[u] = prt;
         if (J.n > 2)
-            scan_string(J, 2, ch, cl, live, hc);
-        emit(J, J.n > 2 ? 2 : 1, ch, cl, live, J.q[0], J.qcount);
+            scan_string(J, first, ch, cl, live, hc);
+        // with three strings or fewer this was the only one left
+        emit(J, J.n <= 3, ch, cl, live, prts, J.q[0], J.qp[0], J.qcount);
     }
     if (hc)
         atomicAdd(&s_hc, hc);
@@ -308,13 +363,13 @@ k_pair_filter(PairJob J, unsigned long long it1, unsigned long long npairs)
         atomicAdd(J.tests, s_hc);
 }
 
-// Queue stage: the candidates that passed strings up to i-1 (qin, count in
-// *qin_count) against string i; survivors to qout (or the heap after the
-// last string).
+// Queue stage i (2 <= i < n): the candidates that passed the earlier
+// stages (qin, partners in qpin, count in *qin_count) against string i;
+// survivors to qout (or the heap after the last string).
 __global__ __launch_bounds__(kTPB) void
-k_pair_queue(PairJob J, int i, const uint2 *qin,
+k_pair_queue(PairJob J, int i, const uint2 *qin, const uint16_t *qpin,
              const unsigned long long *qin_count, uint2 *qout,
-             unsigned long long *qout_count)
+             uint16_t *qpout, unsigned long long *qout_count)
 {
     __shared__ unsigned long long s_hc;
     const int tid = threadIdx.x;
@@ -324,8 +379,8 @@ k_pair_queue(PairJob J, int i, const uint2 *qin,
     const unsigned long long cnt = min(*qin_count, J.qcap);
     for (unsigned long long b0 = (unsigned long long)blockIdx.x * kPairChunk;
          b0 < cnt; b0 += (unsigned long long)gridDim.x * kPairChunk) {
-        uint32_t ch[kPairPer], cl[kPairPer];
-        bool live[kPairPer];
+        uint32_t ch[kPairPer], cl[kPairPer], prt[kPairPer];
+        bool live[kPairPer], pass[kPairPer];
 #pragma unroll
         for (int u = 0; u < kPairPer; u++) {
             const unsigned long long k = b0 + (unsigned long long)u * kTPB + tid;
@@ -333,9 +388,19 @@ k_pair_queue(PairJob J, int i, const uint2 *qin,
             const uint2 v = live[u] ? qin[k] : make_uint2(0u, 0u);
             ch[u] = v.x;
             cl[u] = v.y;
+            prt[u] = live[u] ? (uint32_t)qpin[k] : 1u;
+            // string i is the candidate's partner, or was tested in the
+            // filter stage (string 2 for candidates whose partner is s_2):
+            // it passes without a test
+            pass[u] = live[u] && ((int)prt[u] == i ||
+                                  (prt[u] == 1u && i == 2));
+            live[u] &= !pass[u];
         }
         scan_string(J, i, ch, cl, live, hc);
-        emit(J, i, ch, cl, live, qout, qout_count);
+#pragma unroll
+        for (int u = 0; u < kPairPer; u++)
+            live[u] |= pass[u];
+        emit(J, i >= J.n - 1, ch, cl, live, prt, qout, qpout, qout_count);
     }
     if (hc)
         atomicAdd(&s_hc, hc);
@@ -345,12 +410,13 @@ k_pair_queue(PairJob J, int i, const uint2 *qin,
 }
 
 hipError_t launch_pair_queue(const PairJob &J, int i, const uint2 *qin,
+                             const uint16_t *qpin,
                              const unsigned long long *qin_count, uint2 *qout,
-                             unsigned long long *qout_count, int grid,
-                             hipStream_t st)
+                             uint16_t *qpout, unsigned long long *qout_count,
+                             int grid, hipStream_t st)
 {
     hipLaunchKernelGGL(k_pair_queue, dim3(grid), dim3(kTPB), 0, st, J, i, qin,
-                       qin_count, qout, qout_count);
+                       qpin, qin_count, qout, qpout, qout_count);
     return hipGetLastError();
 }
 

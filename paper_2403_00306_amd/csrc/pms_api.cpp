@@ -856,7 +856,8 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     }
     if (o.path < 0 || o.path > PMS_PATH_PAIR || o.serve_slots < 0 ||
         o.serve_queue < 0 || !(o.serve_launch_ms >= 0.0) ||
-        o.serve_launch_ms > 1000.0 ||
+        o.serve_launch_ms > 1000.0 || o.pair_partner < 0 ||
+        o.pair_partner > 1 ||
         (o.tile_threads != 0 && o.tile_threads != 256 &&
          o.tile_threads != 512)) {
         g_create_error = "bad option value";

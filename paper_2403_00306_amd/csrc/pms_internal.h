@@ -240,12 +240,19 @@ struct PairJob {
     uint64_t *heap;              // survivors (unordered, repeats possible)
     unsigned long long *heap_top;
     unsigned long long heap_cap;
+    const uint32_t *partner;     // per l-mer x of s_1: the string its pairs
+                                 //   take y from (1 = s_2 for every x)
     uint2 *q[2];                 // candidate queues between strings
+    uint16_t *qp[2];             // partner string of each queued candidate
     unsigned long long *qcount;  // entries appended to q[0] by the filter
     unsigned long long qcap;
     unsigned int *overflow;      // set if a queue overflowed
     int n, L, l, d;
 };
+// partner[x] for every l-mer x of s_1: the string j >= 1 whose nearest
+// l-mer is farthest from x (lowest j on ties).
+hipError_t launch_pair_partner(const uint2 *planes, int n, int L,
+                               uint32_t *partner, hipStream_t st);
 hipError_t launch_pair_list(const PairJob &J, hipStream_t st);
 // Candidates of the work items [*J.next, it1) against s_3, survivors to
 // q[0] (count in *J.qcount); then each later string with launch_pair_queue.
@@ -253,9 +260,10 @@ hipError_t launch_pair_filter(const PairJob &J, unsigned long long it1,
                               unsigned long long npairs, int grid,
                               hipStream_t st);
 hipError_t launch_pair_queue(const PairJob &J, int i, const uint2 *qin,
+                             const uint16_t *qpin,
                              const unsigned long long *qin_count, uint2 *qout,
-                             unsigned long long *qout_count, int grid,
-                             hipStream_t st);
+                             uint16_t *qpout, unsigned long long *qout_count,
+                             int grid, hipStream_t st);
 int pair_chunk();
 int pair_blocks_per_cu();
 

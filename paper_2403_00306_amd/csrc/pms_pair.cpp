@@ -1,10 +1,14 @@
 // pms_pair.cpp -- host side of the pair-based path (PMS_PATH_PAIR).
 //
 // Observation 3.3 with q = n: every motif lies in B(x,d) ∩ B(y,d) for an
-// l-mer x of s_1 and an l-mer y of s_2 with d_H(x,y) <= 2d. The host builds
-// the counting tables of those intersections (they depend on D = d_H(x,y)
-// only), then the device lists the compatible pairs, scans their work-item
-// counts and filters every pair's candidates against s_3..s_n.
+// l-mer x of s_1 and an l-mer y of a partner string s_j with
+// d_H(x,y) <= 2d; j is s_2, or (TraverStringRef's string reordering,
+// Sec. 3.2.3) for every x the string whose nearest l-mer is farthest from
+// x, which gives smaller intersections. The host builds the counting tables
+// of those intersections (they depend on D = d_H(x,y) only), then the
+// device picks the partners, lists the compatible pairs, scans their
+// work-item counts and filters every pair's candidates against the other
+// strings.
 #include "pms_host.h"
 
 #include <algorithm>
@@ -106,6 +110,7 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     const size_t o_multi = take(multi.size() * 4);
     const size_t o_bin = take(binom.size() * 8);
     const size_t o_cnt = take(8 * 8);
+    const size_t o_part = take((size_t)L * 4);
     const size_t o_pairs = take(LL * 8);
     const size_t o_chunks = take(LL * 4);
     const size_t o_pos = take((LL + 1) * 8);
@@ -137,6 +142,7 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     J.multi = (const uint32_t *)(b + o_multi);
     J.binom = (const uint64_t *)(b + o_bin);
     J.ntup = (int)tup.size();
+    J.partner = (const uint32_t *)(b + o_part);
     J.pairs = (uint2 *)(b + o_pairs);
     J.chunks = (uint32_t *)(b + o_chunks);
     J.npairs = cnt;
@@ -146,6 +152,7 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     J.qcount = cnt + 4;                 // cnt[4], cnt[5]: the two queues
     J.overflow = (unsigned int *)(cnt + 6);
     J.q[0] = J.q[1] = nullptr;
+    J.qp[0] = J.qp[1] = nullptr;
     J.qcap = 0;
     J.pairs_cap = LL;
     J.item_pos = (const uint64_t *)(b + o_pos);
@@ -156,6 +163,12 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     J.L = L;
     J.l = l;
     J.d = d;
+    const bool per_x = c->opt.pair_partner == 0 && n > 2 && n <= 65536;
+    if (per_x)
+        HIPCHK(c, launch_pair_partner(I.planes, n, L, (uint32_t *)(b + o_part),
+                                      st));
+    else
+        HIPCHK(c, launch_fill_u32((unsigned int *)(b + o_part), L, 1u, st));
     HIPCHK(c, launch_pair_list(J, st));
     unsigned long long *hp = c->pinned + 4;
     HIPCHK(c, hipMemcpyAsync(hp, cnt, 16, hipMemcpyDeviceToHost, st));
@@ -177,10 +190,12 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     const unsigned long long qcap = std::max<unsigned long long>(
         (unsigned long long)pair_chunk(),
         std::min<unsigned long long>(1ull << 26, ncand + pair_chunk()));
-    if ((rc = c->alloc(c->alive, 2 * qcap * sizeof(uint2))))
+    if ((rc = c->alloc(c->alive, 2 * qcap * (sizeof(uint2) + 2))))
         return rc;
     J.q[0] = (uint2 *)c->alive.p;
     J.q[1] = J.q[0] + qcap;
+    J.qp[0] = (uint16_t *)(J.q[1] + qcap);
+    J.qp[1] = J.qp[0] + qcap;
     J.qcap = qcap;
     const unsigned long long per_batch = qcap / pair_chunk();
     const int grid = std::max(1, c->n_cu * c->pair_bpc);
@@ -189,12 +204,15 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
         HIPCHK(c, launch_fill_u64(J.next, 1, lo, st));
         HIPCHK(c, launch_fill_u64(J.qcount, 1, 0, st));
         HIPCHK(c, launch_pair_filter(J, hi, npairs, grid, st));
+        // stages 2..n-1; with s_2 as every partner the filter stage took
+        // string 2, so stage 2 would only copy the queue
         int in = 0;
-        for (int i = 3; i < n; i++) {
+        for (int i = per_x ? 2 : 3; i < n; i++) {
             const int out = in ^ 1;
             HIPCHK(c, launch_fill_u64(J.qcount + out, 1, 0, st));
-            HIPCHK(c, launch_pair_queue(J, i, J.q[in], J.qcount + in,
-                                        J.q[out], J.qcount + out, grid, st));
+            HIPCHK(c, launch_pair_queue(J, i, J.q[in], J.qp[in], J.qcount + in,
+                                        J.q[out], J.qp[out], J.qcount + out,
+                                        grid, st));
             in = out;
         }
     }
