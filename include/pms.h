@@ -175,11 +175,15 @@ int pms_solve_device_noalloc(pms_ctx *ctx, const uint8_t *d_seqs, int n,
  * Hamming distance d of M. q = n is exactly pms_solve. Same arguments,
  * layout, ownership and output as pms_solve, plus q. Runs the tiled path
  * with a per-code count of strings without a d-neighbour (tile suffix at
- * most 8 bases). PMS_EINVAL when q < 1 or q > n, when n - q > 30, when the
- * context's path is forced to PMS_PATH_FILTER or PMS_PATH_BITSET, or when
- * l < 3 or l > 22 (more than 4^14 tiles). The output can be large (a
- * sizeable fraction of 4^l codes when q is small): it is sized on the
- * device before it is copied.
+ * most 8 bases) while its tiles fit (3 <= l <= 22); otherwise, or when the
+ * context's path is forced to PMS_PATH_FILTER, the sample-driven filter
+ * with a miss count per candidate: candidates from the d-spheres of the
+ * l-mers of s_1..s_(n-q+1) (Observation 3.1), each kept once, from its
+ * first such l-mer. PMS_EINVAL when q < 1 or q > n, when n - q > 30, when
+ * the context's path is forced to PMS_PATH_BITSET or PMS_PATH_PAIR, or
+ * when (n-q+1)*(m-l+1) reaches 2^27. The output can be large (a sizeable
+ * fraction of 4^l codes when q is small): it is sized on the device before
+ * it is copied.
  */
 int pms_solve_quorum(pms_ctx *ctx, const char *seqs, int n, int m, int l,
                      int d, int q, const uint64_t **motifs, size_t *count);

@@ -350,6 +350,193 @@ hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
     return hipGetLastError();
 }
 
+// ---- quorum motifs (q < n) on the sample-driven path ---------------------
+// Observation 3.1: the first string in which an (l,d,q)-motif has a
+// d-neighbour is one of s_1..s_R, R = n-q+1, so the candidates are the
+// spheres B(x,d) of the l-mers of those strings. Each candidate carries the
+// number of strings in which it has no d-neighbour; the strings are tested
+// in input order and a candidate is dropped
+//   * at a hit in a string before its reference string (it is generated
+//     again from that earlier string, which is where it is kept),
+//   * once it has missed more than n-q strings;
+// its own reference string passes untested. A survivor is kept only from
+// the first offset of its reference string within distance d of it, so
+// the output is free of repeats. The reference index and the miss count
+// share one word: reference (R*L of them) in the low 27 bits, misses above.
+constexpr uint32_t kQRefBits = 27;
+constexpr uint32_t kQRefMask = (1u << kQRefBits) - 1u;
+
+__global__ __launch_bounds__(kTPB) void
+k_filter_quorum(const InstDev *inst, const uint2 *masks, uint64_t nb, int R,
+                unsigned long long *next_block, uint64_t *heap,
+                unsigned long long *heap_top, unsigned long long heap_cap)
+{
+    __shared__ FilterShared sh;
+    const InstDev I = *inst;
+    const int tid = threadIdx.x;
+    const int L = I.L, d = I.d, l = I.l, n = I.n;
+    const uint32_t T = (uint32_t)(I.n - I.q);    // misses a motif may have
+    const PlaneRow all = planes_row(I.planes, 0);  // strings back to back
+    const uint64_t total = (uint64_t)R * (uint64_t)L * nb;
+    const uint64_t nblocks = (total + kFBlock - 1) / kFBlock;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0)
+            sh.blk = atomicAdd(next_block, 1ull);
+        __syncthreads();
+        const uint64_t b = uni(sh.blk);
+        if (b >= nblocks)
+            break;
+        const uint64_t f0 = b * kFBlock;
+        uint2 c[kFPer];
+        uint32_t ref[kFPer];
+        unsigned int live = 0;
+#pragma unroll
+        for (int k = 0; k < kFPer; k++) {
+            const uint64_t f = f0 + (uint64_t)k * kTPB + tid;
+            c[k] = make_uint2(0, 0);
+            ref[k] = 0;
+            if (f < total) {
+                const uint32_t x = (uint32_t)(f / nb);   // string*L + offset
+                const uint64_t e = f - (uint64_t)x * nb;
+                const uint2 xp = all[x];
+                const uint2 mu = masks[e];
+                c[k] = make_uint2(xp.x ^ mu.x, xp.y ^ mu.y);
+                // misses start at the number of strings before x's string
+                ref[k] = x | ((x / (uint32_t)L) << kQRefBits);
+                live |= 1u << k;
+            }
+        }
+        int nlive = (int)min<uint64_t>((uint64_t)kFBlock, total - f0);
+        for (int si = 0; si < n && nlive > 0; si++) {
+            const BRow yp{(const __attribute__((address_space(1))) unsigned
+                           long long *)(const void *)(I.planes +
+                                                     (size_t)si * L)};
+            uint32_t mind[kFPer];
+            unsigned int test = 0;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++) {
+                mind[k] = 255;
+                const bool own = ((ref[k] & kQRefMask) / (uint32_t)L) ==
+                                 (uint32_t)si;
+                if (((live >> k) & 1u) && !own)
+                    test |= 1u << k;
+            }
+            const int kk = (nlive + kTPB - 1) / kTPB;
+            if (__any(test != 0)) {
+                if (kk <= 1)
+                    scan_string<1>(yp, L, c, mind, d, test);
+                else if (kk <= 2)
+                    scan_string<2>(yp, L, c, mind, d, test);
+                else if (kk <= 4)
+                    scan_string<4>(yp, L, c, mind, d, test);
+                else
+                    scan_string<kFPer>(yp, L, c, mind, d, test);
+            }
+            unsigned int keep = 0, nk = 0;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++) {
+                if (!((live >> k) & 1u))
+                    continue;
+                bool stay = true;
+                if ((test >> k) & 1u) {
+                    const uint32_t rs = (ref[k] & kQRefMask) / (uint32_t)L;
+                    const bool hit = mind[k] <= (uint32_t)d;
+                    if ((uint32_t)si < rs) {
+                        stay = !hit;   // counted among the misses already
+                    } else if (!hit) {
+                        const uint32_t ms = (ref[k] >> kQRefBits) + 1u;
+                        ref[k] = (ref[k] & kQRefMask) | (ms << kQRefBits);
+                        stay = ms <= T;
+                    }
+                }
+                if (stay) {
+                    keep |= 1u << k;
+                    nk++;
+                }
+            }
+            unsigned int tot;
+            const unsigned int pos = blk_exscan(nk, sh.red, &tot);
+            unsigned int w = pos;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++)
+                if ((keep >> k) & 1u) {
+                    sh.cand[w] = c[k];
+                    sh.ref[w] = ref[k];
+                    w++;
+                }
+            __syncthreads();
+            nlive = (int)tot;
+            live = 0;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++) {
+                const int i = k * kTPB + tid;
+                if (i < nlive) {
+                    c[k] = sh.cand[i];
+                    ref[k] = sh.ref[i];
+                    live |= 1u << k;
+                }
+            }
+            __syncthreads();
+        }
+        // keep each motif from the first offset of its reference string
+        unsigned int keep = 0, nk = 0;
+#pragma unroll
+        for (int k = 0; k < kFPer; k++) {
+            if (!((live >> k) & 1u))
+                continue;
+            const uint32_t x = ref[k] & kQRefMask;
+            const uint32_t row0 = x - x % (uint32_t)L;
+            bool first = true;
+            for (uint32_t xj = row0; xj < x && first; xj++) {
+                const uint2 y = all[xj];
+                first = __popc((c[k].x ^ y.x) | (c[k].y ^ y.y)) > d;
+            }
+            if (first) {
+                keep |= 1u << k;
+                nk++;
+            }
+        }
+        unsigned int tot;
+        const unsigned int pos = blk_exscan(nk, sh.red, &tot);
+        if (tid == 0 && tot)
+            sh.off = atomicAdd(heap_top, (unsigned long long)tot);
+        __syncthreads();
+        if (tot) {
+            const unsigned long long off = uni(sh.off);
+            unsigned int w = pos;
+#pragma unroll
+            for (int k = 0; k < kFPer; k++)
+                if ((keep >> k) & 1u) {
+                    if (off + w < heap_cap) {
+                        uint64_t code = 0;
+                        for (int p = 0; p < l; p++)
+                            code = (code << 2) |
+                                   ((((c[k].x >> p) & 1u) << 1) |
+                                    ((c[k].y >> p) & 1u));
+                        heap[off + w] = code;
+                    }
+                    w++;
+                }
+        }
+    }
+}
+
+hipError_t launch_filter_quorum(const InstDev *d_inst, const uint2 *masks,
+                                uint64_t nb, int R,
+                                unsigned long long *next_block, uint64_t *heap,
+                                unsigned long long *heap_top,
+                                unsigned long long heap_cap, int grid,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_filter_quorum, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                       masks, nb, R, next_block, heap, heap_top, heap_cap);
+    return hipGetLastError();
+}
+
+uint32_t filter_quorum_max_refs() { return kQRefMask; }
+
 int filter_blocks_per_cu()
 {
     int nb = 0;

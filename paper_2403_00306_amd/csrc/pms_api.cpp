@@ -410,15 +410,16 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
     if (q < 0 || q > n)
         return c->fail(PMS_EINVAL, "quorum q=%d outside 1..n=%d", q, n);
     const bool quorum = q > 0 && q < n;
+    bool quorum_filter = false;
     if (quorum) {
         if (n - q > kQuorumMaxMiss)
             return c->fail(PMS_EINVAL, "quorum: n-q=%d above %d", n - q,
                            kQuorumMaxMiss);
-        if (forced_path == PMS_PATH_FILTER || forced_path == PMS_PATH_BITSET ||
-            forced_path == PMS_PATH_PAIR)
-            return c->fail(PMS_EINVAL, "quorum (q<n) runs the tiled path "
-                           "only");
-        forced_path = PMS_PATH_TILED;
+        if (forced_path == PMS_PATH_BITSET || forced_path == PMS_PATH_PAIR)
+            return c->fail(PMS_EINVAL, "quorum (q<n) runs the tiled or the "
+                           "filter path");
+        quorum_filter = forced_path == PMS_PATH_FILTER;
+        forced_path = quorum_filter ? PMS_PATH_FILTER : PMS_PATH_TILED;
     }
     if (fixed) {
         if (quorum || !d_out_ext)
@@ -431,12 +432,23 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         return c->fail(PMS_EINVAL, "fixed scratch: l=%d is outside the tiled "
                        "path (3 <= l, at most 4^%d tiles)", l, kMaxTilePrefix);
     if (quorum) {
+        // the tiled path while its tiles fit, else the sample-driven
+        // filter with miss counts (Observation 3.1: references from the
+        // first n-q+1 strings)
         P.s = std::min(P.s, kQuorumMaxSuffix);
-        if (l < 3 || P.s < 3 || l - P.s > kMaxTilePrefix)
-            return c->fail(PMS_EINVAL, "quorum: l=%d outside 3..%d", l,
-                           kQuorumMaxSuffix + kMaxTilePrefix);
-        P.path = PMS_PATH_TILED;
-        P.ntiles = pow4(l - P.s);
+        if (quorum_filter || l < 3 || P.s < 3 || l - P.s > kMaxTilePrefix) {
+            quorum_filter = true;
+            P.path = PMS_PATH_FILTER;
+            P.ntiles = 0;
+            const uint64_t refs = (uint64_t)(n - q + 1) * (uint64_t)(m - l + 1);
+            if (refs >= filter_quorum_max_refs())
+                return c->fail(PMS_EINVAL, "quorum filter: %llu reference "
+                               "l-mers above %u", (unsigned long long)refs,
+                               filter_quorum_max_refs());
+        } else {
+            P.path = PMS_PATH_TILED;
+            P.ntiles = pow4(l - P.s);
+        }
     }
     pms_stats S{};
     S.path = P.path;
@@ -544,11 +556,19 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             HIPCHK(c, launch_fill_u64((unsigned long long *)c->hc_ref.p, L, 0,
                                       st));
             HIPCHK(c, hipEventRecord(c->ev[1], st));
-            HIPCHK(c, launch_filter(d_inst, (const uint2 *)c->masks.p, nb,
-                                    d_next, I.heap, I.heap_top, heap_cap,
-                                    (unsigned long long *)c->hc_ref.p,
-                                    &d_stats->ftests,
-                                    grid_for(c, c->filter_bpc), st));
+            if (quorum_filter)
+                HIPCHK(c, launch_filter_quorum(d_inst,
+                                               (const uint2 *)c->masks.p, nb,
+                                               n - q + 1, d_next, I.heap,
+                                               I.heap_top, heap_cap,
+                                               grid_for(c, c->filter_bpc),
+                                               st));
+            else
+                HIPCHK(c, launch_filter(d_inst, (const uint2 *)c->masks.p, nb,
+                                        d_next, I.heap, I.heap_top, heap_cap,
+                                        (unsigned long long *)c->hc_ref.p,
+                                        &d_stats->ftests,
+                                        grid_for(c, c->filter_bpc), st));
             S.main_launches = 1;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
             HIPCHK(c, hipMemcpyAsync(hp + 1, I.heap_top, 8,

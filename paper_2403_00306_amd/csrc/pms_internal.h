@@ -304,6 +304,16 @@ hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
                          unsigned long long *hc_per_ref,
                          unsigned long long *hexec, int grid, hipStream_t st);
 int filter_blocks_per_cu();
+// Quorum motifs (q = I.q < n) on the sample-driven path: candidates from the
+// l-mers of the first R = n-q+1 strings, kept with at most n-q misses,
+// free of repeats (each from its first reference); unsorted in heap.
+hipError_t launch_filter_quorum(const InstDev *d_inst, const uint2 *masks,
+                                uint64_t nb, int R,
+                                unsigned long long *next_block, uint64_t *heap,
+                                unsigned long long *heap_top,
+                                unsigned long long heap_cap, int grid,
+                                hipStream_t st);
+uint32_t filter_quorum_max_refs();   // R*L must stay below this
 // calibration kernel: the filter's Hamming-test mix from registers only
 hipError_t launch_test_rate(int grid, int iters, uint32_t seed,
                             unsigned int *sink, hipStream_t st);

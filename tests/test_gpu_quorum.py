@@ -117,16 +117,82 @@ def test_quorum_edges(ctx):
     seqs = bytes(rng.choice(ACGT) for _ in range(32 * 30))
     with pytest.raises(pms.PmsError):
         ctx.solve_quorum(seqs, 32, 30, 6, 1, 1)          # n - q = 31
+    # beyond the tiles (4^15 of them at l = 23): the sample-driven filter
     seqs = bytes(rng.choice(ACGT) for _ in range(4 * 40))
-    with pytest.raises(pms.PmsError):
-        ctx.solve_quorum(seqs, 4, 40, 23, 3, 2)          # 4^15 tiles
-    with pms.Context(path=pms.PATH_FILTER) as c2:
-        with pytest.raises(pms.PmsError):
-            c2.solve_quorum(inst.seqs, inst.n, inst.m, 9, 2, 10)
+    got = ctx.solve_quorum(seqs, 4, 40, 23, 3, 2)
+    assert ctx.stats()["path"] == pms.PATH_FILTER
+    assert (got == oracle.q1(seqs, 4, 40, 23, 3, 2)).all()
+    for path in (pms.PATH_BITSET, pms.PATH_PAIR):
+        with pms.Context(path=path) as c2:
+            with pytest.raises(pms.PmsError):
+                c2.solve_quorum(inst.seqs, inst.n, inst.m, 9, 2, 10)
     bad = bytearray(inst.seqs)
     bad[5 * inst.m + 17] = ord("N")
     with pytest.raises(pms.PmsError):
         ctx.solve_quorum(bytes(bad), inst.n, inst.m, 9, 2, 10)
+
+
+@pytest.fixture(scope="module")
+def fctx():
+    c = pms.Context(path=pms.PATH_FILTER)
+    yield c
+    c.close()
+
+
+def test_quorum_filter_path_random_small(fctx):
+    # the sample-driven quorum (references from s_1..s_(n-q+1), a miss
+    # count per candidate, each motif kept from its first reference)
+    rng = random.Random(31)
+    for case in range(40):
+        l = rng.randint(3, 9)
+        d = rng.randint(0, min(3, l - 1))
+        n = rng.randint(2, 9)
+        m = rng.randint(l, 50)
+        q = rng.randint(1, n - 1)
+        seqs = bytes(rng.choice(ACGT) for _ in range(n * m))
+        got = fctx.solve_quorum(seqs, n, m, l, d, q)
+        assert fctx.stats()["path"] == pms.PATH_FILTER
+        want = oracle.q1(seqs, n, m, l, d, q)
+        assert got.shape == want.shape and (got == want).all(), \
+            (case, n, m, l, d, q)
+
+
+@pytest.mark.parametrize("seed,q", [(1, 19), (1, 15), (2, 10), (3, 17)])
+def test_quorum_filter_path_full_9_2(fctx, ctx, seed, q):
+    inst = pmsgen.plain("pms_9_2", seed)
+    say("quorum filter (9,2) seed", seed, "q", q)
+    got = fctx.solve_quorum(inst.seqs, inst.n, inst.m, 9, 2, q)
+    want = oracle.q1(inst.seqs, inst.n, inst.m, 9, 2, q)
+    assert got.shape == want.shape and (got == want).all()
+    assert (ctx.solve_quorum(inst.seqs, inst.n, inst.m, 9, 2, q) == got).all()
+
+
+def test_quorum_filter_path_long_motifs(ctx):
+    # l beyond the tiled path (23..32): the automatic choice is the filter
+    for (n, m, l, d, q) in [(5, 40, 24, 2, 3), (6, 45, 28, 3, 4),
+                            (4, 50, 32, 2, 2), (7, 40, 25, 1, 5)]:
+        inst = pmsgen.planted(l * 3 + d, n, m, l, d)
+        say("quorum long", (n, m, l, d, q))
+        got = ctx.solve_quorum(inst.seqs, n, m, l, d, q)
+        assert ctx.stats()["path"] == pms.PATH_FILTER
+        want = oracle.q1(inst.seqs, n, m, l, d, q)
+        assert got.shape == want.shape and (got == want).all(), (l, d, q)
+        assert code_of(inst.motif) in set(int(v) for v in got)
+
+
+def test_quorum_filter_equals_tiled_13_4(fctx, ctx):
+    # (13,4), n = 20, m = 600, q = 15: the two exact quorum paths agree code
+    # for code; sampled codes are checked against the oracle's count
+    inst = pmsgen.plain("pms_13_4", 1)
+    n, m, l, d, q = inst.n, inst.m, 13, 4, 15
+    tiled = ctx.solve_quorum(inst.seqs, n, m, l, d, q)
+    filt = fctx.solve_quorum(inst.seqs, n, m, l, d, q)
+    assert fctx.stats()["path"] == pms.PATH_FILTER
+    say("quorum (13,4,15):", len(tiled), "motifs")
+    assert tiled.shape == filt.shape and (tiled == filt).all()
+    rng = random.Random(5)
+    for c in rng.sample(list(tiled), min(200, len(tiled))):
+        assert oracle.hit_count(inst.seqs, n, m, l, d, int(c)) >= q
 
 
 def test_quorum_largest_l(ctx):
