@@ -175,6 +175,47 @@ def cpu_baseline(inst, target_s: float = 12.0) -> dict:
                       % (k, L, t, h)}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_checked(np, name: str, insts, results) -> dict:
+    """Compare GPU motif sets with the exact sets the oracle stored in
+    tests/golden/<name> (index n m l d input_sha count hcanon codes_sha
+    codes): the instance's shape and input hash must match, then the count
+    and the hash of the ascending codes (and the codes themselves where
+    stored). Instances without a stored set are not counted."""
+    import hashlib
+    path = os.path.join(GOLDEN, name)
+    stored = {}
+    try:
+        for line in open(path):
+            if not line.strip() or line.startswith("#") or "=" in line:
+                continue
+            t = line.split()
+            stored[int(t[0])] = t
+    except OSError:
+        return {"file": "tests/golden/" + name, "stored": 0, "checked": 0,
+                "matched": 0}
+    checked = matched = 0
+    for i, (x, got) in enumerate(zip(insts, results)):
+        t = stored.get(i)
+        if t is None:
+            continue
+        checked += 1
+        got = np.asarray(got, dtype=np.uint64)
+        ok = ((int(t[1]), int(t[2]), int(t[3]), int(t[4])) ==
+              (x.n, x.m, x.l, x.d) and
+              hashlib.sha256(x.seqs).hexdigest() == t[5] and
+              len(got) == int(t[6]) and
+              hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == t[8])
+        if ok and t[9] not in ("-", "none"):
+            ok = got.tolist() == [int(v) for v in t[9].split(",")]
+        matched += bool(ok)
+    return {"file": "tests/golden/" + name, "stored": len(stored),
+            "instances": len(insts), "checked": checked, "matched": matched,
+            "fraction_checked": checked / max(1, len(insts))}
+
+
 def batch_bench(pms, pmsgen, np, tune: bool) -> dict:
     """256 independent instances: one pms_solve_batch call (one persistent
     launch, replayed as a HIP graph) vs the same instances solved one by
@@ -208,7 +249,9 @@ def batch_bench(pms, pmsgen, np, tune: bool) -> dict:
             len(insts) / t_plain, "batched_ms": 1000 * t_batch,
             "plain_ms": 1000 * t_plain, "batch_kernel_ms": bst["ms_main"],
             "motifs_total": int(sum(len(a) for a in alone)),
-            "batched_equals_plain": bool(same), "autotune_s": t_tune}
+            "batched_equals_plain": bool(same), "autotune_s": t_tune,
+            "oracle_checked": oracle_checked(np, "batched_seed7.txt", insts,
+                                             got)}
 
 
 def quorum_bench(pms, pmsgen, np, torch, dev, reps: int = 3) -> dict:
@@ -417,7 +460,9 @@ def serve_bench(pms, pmsgen, np, count: int, launch_ms: float = 0.0) -> dict:
             "max_inflight": int(st["max_inflight"]),
             "launches": int(st["launches"]),
             "launch_ms_target": launch_ms or None,
-            "mix_equals_saturated_and_alone": bool(same and alone_ok)}
+            "mix_equals_saturated_and_alone": bool(same and alone_ok),
+            "oracle_checked": oracle_checked(
+                np, "served_seed11.txt", [r.inst for r in reqs], res)}
 
 
 def main():
