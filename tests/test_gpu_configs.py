@@ -1,0 +1,78 @@
+"""The batched workload at its full size against the oracle.
+
+The batched configuration is 256 instances of pmsgen.batched(seed=7):
+(l,d) uniform in {(9,2),(11,3),(13,4),(15,5)}, n in [10,40], m in
+[300,1000]. tests/golden/make_golden.py stored, from the oracle (O1) alone,
+the exact motif set of every instance: its size, the hash of its codes and,
+when short, the codes. Every instance is compared.
+"""
+import hashlib
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2403_00306_amd as pms
+import pmsgen
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def read_sets(name):
+    """index -> (n, m, l, d, input_sha, count, codes_sha, codes or None)."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if not line.strip() or line.startswith("#") or "=" in line:
+            continue
+        t = line.split()
+        codes = None
+        if t[9] not in ("-",):
+            codes = [] if t[9] == "none" else [int(x) for x in t[9].split(",")]
+        out[int(t[0])] = (int(t[1]), int(t[2]), int(t[3]), int(t[4]), t[5],
+                          int(t[6]), t[8], codes)
+    return out
+
+
+def check_against(got, rec, inst, what):
+    n, m, l, d, in_sha, count, codes_sha, codes = rec
+    assert (n, m, l, d) == (inst.n, inst.m, inst.l, inst.d), what
+    assert hashlib.sha256(inst.seqs).hexdigest() == in_sha, what
+    got = np.asarray(got, dtype=np.uint64)
+    if codes is not None:
+        np.testing.assert_array_equal(got, np.array(codes, dtype=np.uint64),
+                                      err_msg=what)
+    assert len(got) == count, what
+    assert hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == \
+        codes_sha, what
+
+
+def plant_code(inst):
+    c = 0
+    for ch in inst.motif:
+        c = 4 * c + b"ACGT".index(ch)
+    return c
+
+
+def test_batched_config_all_256_vs_oracle():
+    insts = pmsgen.batched(seed=7, count=256)
+    gold = read_sets("batched_seed7.txt")
+    assert len(gold) == 256, "batched oracle sets incomplete: %d" % len(gold)
+    say("batched config: 256 instances")
+    with pms.Context() as c:
+        got = c.solve_batch(insts)
+        st = c.stats()
+        again = c.solve_batch(insts)     # graph replay
+        assert c.stats()["graph_replayed"] == 1
+    say("batched: %d tiles, %d passes" % (st["tiles"], st["tile_passes"]))
+    for i, x in enumerate(insts):
+        check_against(got[i], gold[i], x, "batched instance %d" % i)
+        np.testing.assert_array_equal(got[i], again[i])
+        assert plant_code(x) in set(int(v) for v in got[i])
