@@ -307,8 +307,10 @@ typedef struct {
     int path;                 /* PMS_PATH_* actually used */
     int tile_suffix;          /* tiled/bitset: bases per tile suffix (s) */
     double ms_total;          /* host wall time of the call */
-    double ms_index;          /* pack + l-mer index kernels */
-    double ms_main;           /* filter / tiled / bitset kernels */
+    double ms_index;          /* pack + l-mer index kernels (bitset
+                                 path: and the per-tile string order) */
+    double ms_main;           /* filter / tiled kernels; bitset path: its
+                                 n pass launches */
     double ms_output;         /* compaction, ordering, copies */
     uint64_t main_launches;   /* launches of the main kernel */
     uint64_t hcanon;          /* filter path: Hamming tests in the

@@ -27,6 +27,8 @@
 // every live tile: read 4^s bits, AND the string's union, write back.
 #include "pms_internal.h"
 
+#include <type_traits>
+
 namespace pms {
 
 // The tile code is written for a workgroup of TPB threads: kTPB (256, four
@@ -207,12 +209,24 @@ __device__ __forceinline__ void or64_at(TileShared &sh, uint32_t off,
 // more than kTPB/2 entries every wave walks the same l-mers (64 read at
 // once, then broadcast into scalar registers by readlane); a smaller
 // sphere is repeated in kTPB/bs lane groups that walk different l-mers.
-template <int TPB>
-__device__ unsigned long long mark_string(const InstDev &I, int seq,
-                                          uint32_t Phi, uint32_t Plo,
-                                          uint32_t premask, TileShared &sh,
-                                          const Tables &tb)
+// A caller-supplied hook(y0) runs in every listing round (y0 = the round's
+// first l-mer), unconditionally, after the round's l-mer loads are issued
+// and before their values are used: memory loads the hook issues then queue
+// behind them, so the listing does not wait for the hook's loads (the memory
+// counter is waited on in issue order; a branch around the hook would make
+// the compiler wait for everything at the join).
+struct NoHook {
+    __device__ void operator()(int) const {}
+};
+
+template <int TPB, class Hook = NoHook>
+__device__ __forceinline__ unsigned long long
+mark_string(const InstDev &I, int seq, uint32_t Phi, uint32_t Plo,
+            uint32_t premask, TileShared &sh, const Tables &tb,
+            Hook &&hook = Hook())
 {
+    constexpr bool kHook = !std::is_same<typename std::decay<Hook>::type,
+                                         NoHook>::value;
     constexpr int kTPB = TPB;
     constexpr int kYPer = (kYChunk + TPB - 1) / TPB;
     const int tid = threadIdx.x;
@@ -240,20 +254,54 @@ __device__ unsigned long long mark_string(const InstDev &I, int seq,
         __syncthreads();
         uint32_t ys[kYPer];
         int rr[kYPer];
+        if constexpr (kHook) {
+            // every load of the round first, then the hook, then the tests;
+            // the code words through a plain global pointer, which the
+            // compiler may not move past the hook (it would sink a
+            // constant-space load into the branch that uses it)
+            typedef const __attribute__((address_space(1))) uint32_t g_u32;
+            g_u32 *ycg = (g_u32 *)(const void *)(I.codes + (size_t)seq * I.L);
+            uint2 yv[kYPer];
+            uint32_t ylv[kYPer];
 #pragma unroll
-        for (int u = 0; u < kYPer; u++) {
-            const int j = tid + u * kTPB;
-            rr[u] = -1;
-            if (j < ny) {
-                // both loads in flight together: one memory round trip
-                const uint2 y = yp[y0 + j];
-                const uint32_t yl = ycl[2 * (y0 + j)];
-                asm volatile("" : : "v"(yl));
-                const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) & premask);
-                if (k <= d) {
+            for (int u = 0; u < kYPer; u++) {
+                const int j = min(tid + u * kTPB, ny - 1);
+                yv[u] = yp[y0 + j];
+                ylv[u] = ycg[2 * (y0 + j)];
+            }
+            // keep the scheduler from moving any of those loads past the
+            // hook's
+            asm volatile("" : : : "memory");
+            hook(y0);
+#pragma unroll
+            for (int u = 0; u < kYPer; u++) {
+                const int j = tid + u * kTPB;
+                rr[u] = -1;
+                const int k = __popc(((yv[u].x ^ Phi) | (yv[u].y ^ Plo)) &
+                                     premask);
+                if (j < ny && k <= d) {
                     rr[u] = d - k;
-                    ys[u] = list_entry(yl & sufmask);
+                    ys[u] = list_entry(ylv[u] & sufmask);
                     atomicAdd(&sh.rcnt[d - k], 1);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kYPer; u++) {
+                const int j = tid + u * kTPB;
+                rr[u] = -1;
+                if (j < ny) {
+                    // both loads in flight together: one memory round trip
+                    const uint2 y = yp[y0 + j];
+                    const uint32_t yl = ycl[2 * (y0 + j)];
+                    asm volatile("" : : "v"(yl));
+                    const int k = __popc(((y.x ^ Phi) | (y.y ^ Plo)) &
+                                         premask);
+                    if (k <= d) {
+                        rr[u] = d - k;
+                        ys[u] = list_entry(yl & sufmask);
+                        atomicAdd(&sh.rcnt[d - k], 1);
+                    }
                 }
             }
         }
@@ -513,6 +561,71 @@ struct StatAcc {
 };
 
 // One tile of the tiled path.
+// Strings in ascending order of the word marks their reaching l-mers would
+// make on a tile (the sizes of their word-level spheres): small unions empty
+// the intersection soonest and cost least, as PMS8's rows sorted by size do
+// (Sec. 3.2.4). Any order gives the same set. With oe > 0 the masses are
+// summed over the 4^oe sibling tiles that share the prefix without its last
+// oe bases (an l-mer at distance k from that shorter prefix is at k + j from
+// C(oe,j) 3^j of the siblings). Writes sh.torder[0..n); ends with a barrier.
+// The caller's previous use of sh.U must be over by the first barrier here.
+template <int TPB>
+__device__ void order_strings(const InstDev &I, uint32_t Phi, uint32_t Plo,
+                              uint32_t premask, int oe, TileShared &sh,
+                              const Tables &tb)
+{
+    constexpr int kWaves = TPB / 64;
+    const int tid = threadIdx.x;
+    const int q = I.s - 3, pl = I.l - I.s;
+    const uint32_t omask = premask & ~(((1u << oe) - 1u) << (pl - oe));
+    if (tid <= I.d) {
+        uint32_t v = 0, cf = 1;
+        for (int j = 0; j <= oe && tid + j <= I.d; j++) {
+            v += cf * (uint32_t)tb.ball_off[q * 8 + min(I.d - tid - j, q) + 1];
+            cf = cf * 3u * (uint32_t)(oe - j) / (uint32_t)(j + 1);
+        }
+        sh.cw[tid] = v;   // indexed by k, not by the radius d - k
+    }
+    __syncthreads();
+    // one wave per string; each lane loads kOrdPer l-mers at once so that a
+    // string costs about one round trip to L2
+    constexpr int kOrdPer = TPB >= kTPBWide ? 4 : 8;
+    const int wid = tid >> 6, lane = tid & 63;
+    for (int i = wid; i < I.n; i += kWaves) {
+        const PlaneRow yp = planes_row(I.planes, (size_t)i * I.L);
+        uint32_t mass = 0;
+        for (int j0 = lane; j0 < I.L; j0 += 64 * kOrdPer) {
+            uint2 y[kOrdPer];
+#pragma unroll
+            for (int u = 0; u < kOrdPer; u++)
+                y[u] = yp[min(j0 + 64 * u, I.L - 1)];
+#pragma unroll
+            for (int u = 0; u < kOrdPer; u++) {
+                const int k = __popc(((y[u].x ^ Phi) | (y[u].y ^ Plo)) &
+                                     omask);
+                if (j0 + 64 * u < I.L && k <= I.d)
+                    mass += sh.cw[k];
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            mass += __shfl_xor(mass, o, 64);
+        if (lane == 0)
+            sh.mass[i] = mass;
+    }
+    __syncthreads();
+    if (tid < I.n) {
+        const uint32_t mi = sh.mass[tid];
+        int rank = 0;
+        for (int j = 0; j < I.n; j++) {
+            const uint32_t mj = sh.mass[j];
+            rank += (mj < mi) || (mj == mi && j < tid);
+        }
+        sh.torder[rank] = tid;
+    }
+    __syncthreads();
+}
+
 template <int TPB>
 __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
                          const Tables &tb, StatAcc &acc, int order_mode)
@@ -533,67 +646,18 @@ __device__ void run_tile(const InstDev &I, uint64_t t, TileShared &sh,
     uint32_t Phi, Plo;
     prefix_planes(t, pl, Phi, Plo);
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
-    // Strings in ascending order of the word marks their reaching l-mers
-    // would make on this tile (the sizes of their word-level spheres): small
-    // unions empty the intersection soonest and cost least, as PMS8's rows
-    // sorted by size do (Sec. 3.2.4). Any order gives the same set. The host turns it on where a pass's marks outweigh the
+    // Strings in ascending order of their sphere mass on this tile (see
+    // order_strings). The host turns it on where a pass's marks outweigh the
     // n*L prefix tests it costs. order_mode: 0 keeps the previous tile's
     // order, 1 orders for this tile alone, 2 for the kOrderReuse sibling
-    // tiles that share the prefix without its last e = log4(kOrderReuse)
-    // bases (the sum of their masses: an l-mer at distance k from that
-    // shorter prefix is at k + j from C(e,j) 3^j of the siblings).
+    // tiles that share the prefix without its last log4(kOrderReuse) bases.
     const bool tile_order = I.tile_order != 0 && I.n <= kOrderMax;
     const bool make_order = tile_order && order_mode != 0;
     const int oe = (order_mode == 2) ? min(kOrderReuseLog4, pl) : 0;
-    const uint32_t omask = premask & ~(((1u << oe) - 1u) << (pl - oe));
-    if (make_order && tid <= I.d) {
-        uint32_t v = 0, cf = 1;
-        for (int j = 0; j <= oe && tid + j <= I.d; j++) {
-            v += cf * (uint32_t)tb.ball_off[q * 8 + min(I.d - tid - j, q) + 1];
-            cf = cf * 3u * (uint32_t)(oe - j) / (uint32_t)(j + 1);
-        }
-        sh.cw[tid] = v;   // indexed by k, not by the radius d - k
-    }
-    __syncthreads();   // the previous tile may still be reading sh.U
-    if (make_order) {
-        // one wave per string; each lane loads kOrdPer l-mers at once so
-        // that a string costs about one round trip to L2
-        constexpr int kOrdPer = TPB >= kTPBWide ? 4 : 8;
-        const int wid = tid >> 6, lane = tid & 63;
-        for (int i = wid; i < I.n; i += kWaves) {
-            const PlaneRow yp = planes_row(I.planes, (size_t)i * I.L);
-            uint32_t mass = 0;
-            for (int j0 = lane; j0 < I.L; j0 += 64 * kOrdPer) {
-                uint2 y[kOrdPer];
-#pragma unroll
-                for (int u = 0; u < kOrdPer; u++)
-                    y[u] = yp[min(j0 + 64 * u, I.L - 1)];
-#pragma unroll
-                for (int u = 0; u < kOrdPer; u++) {
-                    const int k = __popc(((y[u].x ^ Phi) | (y[u].y ^ Plo)) &
-                                         omask);
-                    if (j0 + 64 * u < I.L && k <= I.d)
-                        mass += sh.cw[k];
-                }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-                mass += __shfl_xor(mass, o, 64);
-            if (lane == 0)
-                sh.mass[i] = mass;
-        }
-        __syncthreads();
-        if (tid < I.n) {
-            const uint32_t mi = sh.mass[tid];
-            int rank = 0;
-            for (int j = 0; j < I.n; j++) {
-                const uint32_t mj = sh.mass[j];
-                rank += (mj < mi) || (mj == mi && j < tid);
-            }
-            sh.torder[rank] = tid;
-        }
-        __syncthreads();
-    }
+    if (make_order)
+        order_strings<TPB>(I, Phi, Plo, premask, oe, sh, tb);
+    else
+        __syncthreads();   // the previous tile may still be reading sh.U
 
     // the running intersection; every code is in it before the first string
     unsigned long long A[kWordsPerThread];
@@ -1088,69 +1152,145 @@ int tiled_blocks_per_cu(bool wide)
 
 // ---- memory-heavy bitset path ---------------------------------------------
 
+// raw buffer access (CDNA): the descriptor's last word for untyped 32-bit
+// data, and the cache-policy operand that marks an access non-temporal
+constexpr int kBufDword3 = 0x00020000;
+constexpr int kBufNonTemporal = 2;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Byte p[i] (i uniform) through a scalar load of its aligned 32-bit word:
+// scalar loads are waited on by their own counter, so this read does not
+// wait for the vector stores still in flight (the previous tile's A). The
+// buffer behind p must extend to the end of that word. Used for bytes that
+// this launch reads before any write to them (the previous pass's liveness)
+// or never writes (the string order).
+__device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, uint64_t i)
+{
+    typedef const __attribute__((address_space(4))) uint32_t c_u32;
+    const uintptr_t a = (uintptr_t)(p + i);
+    const uint32_t w = *(c_u32 *)(const void *)(a & ~(uintptr_t)3);
+    return (w >> (8u * (uint32_t)(a & 3u))) & 0xffu;
+}
+
 // One string pass of the memory-heavy path over every live tile. A tile's
-// words of the resident intersection A are loaded into registers before
-// its sphere union is marked in LDS, so the device-memory latency overlaps
-// the marking; then A &= U is written back (U read and cleared in one LDS
-// instruction) and the tile's liveness recorded for the next pass. Tiles
-// are taken in chunks of kBitsetChunk from a counter, so that workgroups
-// stay balanced as tiles die out (the host sizes the chunks so that every
-// workgroup gets several). 256 threads: the 16 words of A per thread stay
-// in registers across the marking without spills.
-template <int TPB>
+// words of the resident intersection A are loaded into registers while its
+// string's l-mers are listed and its sphere union marked in LDS; then
+// A &= U is written back (U read and cleared in one LDS instruction) and
+// the tile's liveness recorded. Pass 0 runs over every tile; each pass
+// appends its live tiles to a list that the next pass runs over, so no pass
+// scans dead tiles and the work shares stay even when the live tiles are
+// clustered. Items are taken in chunks from a counter, sized from the
+// list's length so that every workgroup gets several. 256 threads: the 16
+// words of A per thread stay in registers without spills. With ord (n bytes
+// per tile, from k_bitset_order) pass p ANDs each tile's p-th string in its
+// own order, else string I.order[p] on every tile.
+//
+// cnt[2p] is pass p's chunk counter, cnt[2p+1] the length of the list pass
+// p writes (lists[(p+1)&1]); all start at zero. kLoad is false for pass 0
+// only, where A is all ones, nothing is read and the items are the tiles.
+template <int TPB, bool kLoad>
 __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
                             unsigned long long *A, uint8_t *alive,
-                            unsigned int *next, int chunk, TileStats *stats)
+                            const uint8_t *ord, unsigned int *cnt,
+                            uint32_t *const *lists, int chunk0,
+                            TileStats *stats, TileShared &sh,
+                            unsigned int &s_chunk)
 {
     constexpr int kTPB = TPB;
     constexpr int kPer = kMaxWords / TPB;   // words of A per thread
-    __shared__ TileShared sh;
-    __shared__ unsigned int s_chunk;
+    typedef const __attribute__((address_space(4))) uint32_t c_u32;
     const InstDev I = uni_desc(*inst);
     const int tid = threadIdx.x;
     const int s = I.s, q = s - 3, pl = I.l - s;
     const int W = 1 << (2 * q);
     const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
-    const int seq = uni(I.order[pass]);
+    const int gseq = uni(I.order[pass]);
+    const uint32_t *list_in = lists[pass & 1];
+    uint32_t *list_out = lists[(pass + 1) & 1];
+    // items: the tiles (pass 0) or the previous pass's live tiles
+    uint64_t nitems = I.ntiles;
+    uint64_t chunk = (uint64_t)chunk0;
+    if (kLoad) {
+        nitems = ((c_u32 *)(const void *)cnt)[2 * pass - 1];
+        chunk = min<uint64_t>(8, max<uint64_t>(1, nitems /
+                                                      (8ull * gridDim.x)));
+    }
     for (int i = tid; i < 256; i += kTPB)
         sh.m3[i] = tb.m3[i];
     for (int i = tid; i < kMaxWords; i += kTPB)
         sh.U[i] = 0;
     unsigned long long marks = 0, passes = 0;
-    const uint64_t nchunks = (I.ntiles + chunk - 1) / (uint64_t)chunk;
+    const uint64_t nchunks = (nitems + chunk - 1) / chunk;
     for (;;) {
         __syncthreads();
         if (tid == 0)
-            s_chunk = atomicAdd(next, 1u);
+            s_chunk = atomicAdd(&cnt[2 * pass], 1u);
         __syncthreads();
         const uint64_t ch = uni(s_chunk);
         if (ch >= nchunks)
             break;
-        const uint64_t t1 = min((ch + 1) * (uint64_t)chunk, I.ntiles);
-        for (uint64_t t = ch * (uint64_t)chunk; t < t1; t++) {
-            if (pass > 0 && alive[t] == 0)
-                continue;
+        const uint64_t i1 = min((ch + 1) * chunk, nitems);
+        for (uint64_t it = ch * chunk; it < i1; it++) {
+            // the list entry through a scalar load: it does not wait for
+            // the previous tile's stores
+            const uint64_t t =
+                kLoad ? (uint64_t)((c_u32 *)(const void *)list_in)[it] : it;
+            const int seq =
+                ord ? (int)uniform_byte(ord, t * (uint64_t)I.n + pass) : gseq;
             unsigned long long *Ag = A + t * (uint64_t)W;
             unsigned long long a[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; k++) {
-                const int w = tid + k * kTPB;
-                // A is streamed once per pass: non-temporal access
-                a[k] = (pass > 0 && w < W) ? __builtin_nontemporal_load(&Ag[w])
-                                           : ~0ull;
-            }
             uint32_t Phi, Plo;
             prefix_planes(t, pl, Phi, Plo);
-            marks += mark_string<kTPB>(I, seq, Phi, Plo, premask, sh, tb);
+            if constexpr (kLoad) {
+                // A's words are loaded while the string's l-mers are listed
+                // and its union marked, issued after the listing's own loads
+                // so that the listing waits for its own loads only. Through a
+                // buffer resource over the tile's W words: one address
+                // register per load, and an access out of its range reads 0
+                // without touching memory. That covers words past W (never
+                // stored) and the later listing rounds of a long string,
+                // whose resource has no range at all.
+#pragma unroll
+                for (int k = 0; k < kPer; k++)
+                    a[k] = 0;
+                marks += mark_string<kTPB>(
+                    I, seq, Phi, Plo, premask, sh, tb, [&](int y0) {
+                        const __amdgpu_buffer_rsrc_t rA =
+                            __builtin_amdgcn_make_buffer_rsrc(
+                                Ag, 0, y0 == 0 ? W * 8 : 0, kBufDword3);
+#pragma unroll
+                        for (int k = 0; k < kPer; k++) {
+                            // streamed once per pass: non-temporal access
+                            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(
+                                rA, (uint32_t)(tid + k * kTPB) * 8u, 0,
+                                kBufNonTemporal);
+                            a[k] |= ((unsigned long long)v.y << 32) | v.x;
+                        }
+                    });
+            } else {
+#pragma unroll
+                for (int k = 0; k < kPer; k++)
+                    a[k] = ~0ull;
+                marks += mark_string<kTPB>(I, seq, Phi, Plo, premask, sh, tb);
+            }
             passes++;
+            // A's words are needed now: one wait for all of them here, so
+            // that the stores below are not each followed by a wait for
+            // every outstanding memory operation
+#pragma unroll
+            for (int k = 0; k < kPer; k++)
+                asm volatile("" : "+v"(a[k]));
             int nz = 0;
             uint32_t tw = (uint32_t)tid;
             asm volatile("" : "+v"(tw));
             const uint32_t pbase = wpos(tw);
+            // a tile of at least kTPB words (s >= 7) takes whole rows of
+            // kTPB words, a uniform test; a smaller one its first W lanes
+            const bool rows = W >= kTPB;
 #pragma unroll
             for (int k = 0; k < kPer; k++) {
                 const int w = tid + k * kTPB;
-                if (w < W) {
+                if (rows ? (k * kTPB < W) : (k == 0 && tid < W)) {
                     const unsigned long long u = __hip_atomic_exchange(
                         &sh.U[pbase ^ wpos((uint32_t)(k * kTPB))], 0ull,
                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1160,8 +1300,11 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
                 }
             }
             const int any = __syncthreads_or(nz);
-            if (tid == 0)
+            if (tid == 0) {
                 alive[t] = (uint8_t)(any != 0);
+                if (any)
+                    list_out[atomicAdd(&cnt[2 * pass + 1], 1u)] = (uint32_t)t;
+            }
         }
     }
     if (tid == 0 && stats) {
@@ -1170,21 +1313,127 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
     }
 }
 
-__global__ __launch_bounds__(kTPB, kTPB / 64) void
+#ifndef PMS_BITSET_TPB
+#define PMS_BITSET_TPB 256
+#endif
+constexpr int kBitsetTPB = PMS_BITSET_TPB;
+
+__global__ __launch_bounds__(kBitsetTPB, kBitsetTPB / 64) void
 k_bitset_pass(const InstDev *inst, int pass, Tables tb,
-              unsigned long long *A, uint8_t *alive, unsigned int *next,
-              int chunk, TileStats *stats)
+              unsigned long long *A, uint8_t *alive, const uint8_t *ord,
+              unsigned int *cnt, uint32_t *list0, uint32_t *list1, int chunk0,
+              TileStats *stats)
 {
-    bitset_pass<kTPB>(inst, pass, tb, A, alive, next, chunk, stats);
+    __shared__ TileShared sh;
+    __shared__ unsigned int s_chunk;
+    uint32_t *const lists[2] = {list0, list1};
+    if (pass == 0)
+        bitset_pass<kBitsetTPB, false>(inst, pass, tb, A, alive, ord, cnt,
+                                       lists, chunk0, stats, sh, s_chunk);
+    else
+        bitset_pass<kBitsetTPB, true>(inst, pass, tb, A, alive, ord, cnt,
+                                      lists, chunk0, stats, sh, s_chunk);
 }
 
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              unsigned int *next, int chunk, TileStats *stats,
-                              int grid, hipStream_t st)
+                              const uint8_t *ord, unsigned int *cnt,
+                              uint32_t *list0, uint32_t *list1, int chunk0,
+                              TileStats *stats, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kTPB), 0, st, d_inst,
-                       pass, tb, A, alive, next, chunk, stats);
+    hipLaunchKernelGGL(k_bitset_pass, dim3(grid), dim3(kBitsetTPB), 0, st,
+                       d_inst, pass, tb, A, alive, ord, cnt, list0, list1,
+                       chunk0, stats);
+    return hipGetLastError();
+}
+
+// The bitset path's string order, per tile: ord[t*n + p] is the string that
+// pass p ANDs into tile t, the strings in ascending order of their sphere
+// mass on the tile (the masses order_strings computes for a tile alone;
+// ties by string index). First k_bitset_mass, one thread per (tile,
+// string): the string's l-mers are staged in LDS and every lane tests each
+// of them (a broadcast read) against its own tile's prefix. Then
+// k_bitset_rank, one thread per tile. The caller guarantees n <= kOrderMax.
+constexpr int kOrderTPB = 128;
+constexpr int kOrderChunk = 1024;   // l-mers staged at a time
+
+__global__ __launch_bounds__(kOrderTPB) void
+k_bitset_mass(const InstDev *inst, Tables tb, uint32_t *mass)
+{
+    __shared__ unsigned long long yrow[kOrderChunk];
+    __shared__ uint32_t cw[kMaxL + 1];
+    const InstDev I = uni_desc(*inst);
+    const int tid = threadIdx.x, i = blockIdx.y;
+    const int q = I.s - 3, pl = I.l - I.s, d = I.d, n = I.n, L = I.L;
+    const uint32_t premask = (pl >= 32) ? ~0u : ((1u << pl) - 1u);
+    // word marks of one reaching l-mer at prefix distance k (0 past d; the
+    // distance is at most pl <= kMaxL)
+    for (int k = tid; k <= kMaxL; k += kOrderTPB)
+        cw[k] = k <= d ? (uint32_t)tb.ball_off[q * 8 + min(d - k, q) + 1] : 0u;
+    const unsigned long long *row =
+        (const unsigned long long *)(const void *)I.planes + (size_t)i * L;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kOrderTPB; t0 < I.ntiles;
+         t0 += (uint64_t)gridDim.x * kOrderTPB) {
+        const uint64_t t = t0 + tid;
+        uint32_t Phi, Plo;
+        prefix_planes(t < I.ntiles ? t : 0, pl, Phi, Plo);
+        uint32_t m = 0;
+        for (int j0 = 0; j0 < L; j0 += kOrderChunk) {
+            const int cnt = min(kOrderChunk, L - j0);
+            __syncthreads();   // cw is set; the previous chunk has been read
+            for (int j = tid; j < cnt; j += kOrderTPB)
+                yrow[j] = row[j0 + j];
+            __syncthreads();
+#pragma unroll 8
+            for (int j = 0; j < cnt; j++) {
+                const unsigned long long y = yrow[j];
+                const int k = __popc((((uint32_t)y ^ Phi) |
+                                      ((uint32_t)(y >> 32) ^ Plo)) &
+                                     premask);
+                m += cw[k];
+            }
+        }
+        if (t < I.ntiles)
+            mass[t * (uint64_t)n + i] = m;
+    }
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_bitset_rank(const InstDev *inst, const uint32_t *mass, uint8_t *ord)
+{
+    const InstDev I = uni_desc(*inst);
+    const int n = I.n;
+    for (uint64_t t = (uint64_t)blockIdx.x * kTPB + threadIdx.x; t < I.ntiles;
+         t += (uint64_t)gridDim.x * kTPB) {
+        const uint32_t *mt = mass + t * (uint64_t)n;
+        for (int i = 0; i < n; i++) {
+            const uint32_t mi = mt[i];
+            int rank = 0;
+            for (int j = 0; j < n; j++) {
+                const uint32_t mj = mt[j];
+                rank += (mj < mi) || (mj == mi && j < i);
+            }
+            ord[t * (uint64_t)n + rank] = (uint8_t)i;
+        }
+    }
+}
+
+hipError_t launch_bitset_order(const InstDev *d_inst, Tables tb,
+                               uint32_t *mass, uint8_t *ord, uint64_t ntiles,
+                               int n, hipStream_t st)
+{
+    const uint64_t mblocks = (ntiles + kOrderTPB - 1) / kOrderTPB;
+    hipLaunchKernelGGL(k_bitset_mass,
+                       dim3((unsigned)std::min<uint64_t>(mblocks, 65535),
+                            (unsigned)n),
+                       dim3(kOrderTPB), 0, st, d_inst, tb, mass);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const uint64_t rblocks = (ntiles + kTPB - 1) / kTPB;
+    hipLaunchKernelGGL(k_bitset_rank,
+                       dim3((unsigned)std::min<uint64_t>(rblocks, 65535)),
+                       dim3(kTPB), 0, st, d_inst, mass, ord);
     return hipGetLastError();
 }
 
@@ -1192,7 +1441,8 @@ int bitset_blocks_per_cu()
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bitset_pass,
-                                                     kTPB, 0) != hipSuccess ||
+                                                     kBitsetTPB, 0) !=
+            hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;

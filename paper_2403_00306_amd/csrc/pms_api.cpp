@@ -722,23 +722,46 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             const uint64_t words = pow4(l - 3);
             if ((rc = c->alloc(c->bitset, words * 8)))
                 return rc;
-            if ((rc = c->alloc(c->alive, ntiles)))
+            // one buffer: the alive flags; (n <= kOrderMax) each tile's
+            // string order; 2n pass counters; two lists of live tiles; the
+            // per-tile string masses the order is made from. The bytes are
+            // read by 32-bit words, so the counters start on a whole word
+            // past them.
+            if (ntiles >= ((uint64_t)1 << 32))
+                return c->fail(PMS_ENOMEM, "bitset path: 4^%d tiles", l - P.s);
+            const bool border = n <= kOrderMax;
+            const uint64_t cnt_off =
+                (ntiles * (border ? 1 + n : 1) + 4 + 15) & ~(uint64_t)15;
+            const uint64_t list_off = cnt_off + (uint64_t)8 * n;
+            const uint64_t mass_off = list_off + ntiles * 8;
+            if ((rc = c->alloc(c->alive, mass_off + (border ? ntiles * 4 * n
+                                                             : 0))))
                 return rc;
+            uint8_t *d_alive = (uint8_t *)c->alive.p;
+            uint8_t *d_ord = border ? d_alive + ntiles : nullptr;
+            unsigned int *d_cnt = (unsigned int *)(d_alive + cnt_off);
+            uint32_t *d_list0 = (uint32_t *)(d_alive + list_off);
+            uint32_t *d_list1 = d_list0 + ntiles;
             base = (char *)c->arena.p;
             const int grid = grid_for(c, c->tiled_bpc);
-            // tiles in chunks of up to 8, at least 8 chunks per workgroup
+            if (border)
+                HIPCHK(c, launch_bitset_order(d_inst, c->tb,
+                                              (uint32_t *)(d_alive + mass_off),
+                                              d_ord, ntiles, n, st));
+            HIPCHK(c, launch_fill_u64((unsigned long long *)d_cnt, n, 0, st));
+            // ms_main covers the passes alone; the order counts as index
+            HIPCHK(c, hipEventRecord(c->ev[1], st));
+            // pass 0: tiles in chunks of up to 8, at least 8 chunks per
+            // workgroup (later passes size theirs on the device)
             const int bgrid = grid_for(c, c->bitset_bpc);
             const int bchunk = (int)std::max<uint64_t>(
                 1, std::min<uint64_t>(8, ntiles / ((uint64_t)bgrid * 8)));
-            for (int pass = 0; pass < n; pass++) {
-                // every pass takes tiles from a counter of its own
-                HIPCHK(c, launch_fill_u64(d_next, 1, 0, st));
+            for (int pass = 0; pass < n; pass++)
                 HIPCHK(c, launch_bitset_pass(d_inst, pass, c->tb,
                                              (unsigned long long *)c->bitset.p,
-                                             (uint8_t *)c->alive.p,
-                                             (unsigned int *)d_next, bchunk,
-                                             d_stats, bgrid, st));
-            }
+                                             d_alive, d_ord, d_cnt, d_list0,
+                                             d_list1, bchunk, d_stats, bgrid,
+                                             st));
             S.main_launches = n;
             HIPCHK(c, hipEventRecord(c->ev[2], st));
             HIPCHK(c, launch_bitset_count(d_inst,

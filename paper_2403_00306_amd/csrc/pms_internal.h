@@ -278,10 +278,19 @@ int tiled_quorum_blocks_per_cu();
 // Memory-heavy bitset path: one pass per string over the whole 4^l space.
 // One string pass of the memory-heavy path; tiles are taken `chunk` at a
 // time from *next (cleared by the caller before the launch).
+// pass p of the bitset path: cnt holds 2n zeroed counters (chunk counter
+// and output list length per pass); list0/list1 hold ntiles tile indices
+// each (the live tiles, ping-pong); chunk0 = tiles per chunk in pass 0
 hipError_t launch_bitset_pass(const InstDev *d_inst, int pass, Tables tb,
                               unsigned long long *A, uint8_t *alive,
-                              unsigned int *next, int chunk, TileStats *stats,
-                              int grid, hipStream_t st);
+                              const uint8_t *ord, unsigned int *cnt,
+                              uint32_t *list0, uint32_t *list1, int chunk0,
+                              TileStats *stats, int grid, hipStream_t st);
+// per-tile string order of the bitset path: n bytes per tile in ord
+// (n <= kOrderMax), through n 32-bit masses per tile in mass
+hipError_t launch_bitset_order(const InstDev *d_inst, Tables tb,
+                               uint32_t *mass, uint8_t *ord, uint64_t ntiles,
+                               int n, hipStream_t st);
 int bitset_blocks_per_cu();
 hipError_t launch_bitset_count(const InstDev *d_inst,
                                const unsigned long long *A,
