@@ -327,18 +327,19 @@ void build_tables(std::vector<uint16_t> &ball, std::vector<int> &base,
                 c += e.first < w;
             off[q * 8 + w] = c;
         }
-        // Within each weight, deal the masks out round-robin by their low
-        // six bits: a wave's 64 lanes then take masks with distinct word
-        // residues, XOR with the l-mer's word index keeps them distinct,
-        // and the 64-bit word ORs of one instruction fall in distinct LDS
-        // bank pairs.
+        // Within each weight, deal the masks out round-robin by the bank
+        // bits of their word position, wpos(mask) & 31: consecutive entries
+        // (the lanes of one LDS instruction) then fall in distinct banks as
+        // far as the weight's masks allow, and XOR with the l-mer's word
+        // position, the same in every lane, keeps them distinct.
         for (int w = 0; w <= q; w++) {
-            std::vector<std::vector<int>> byres(64);
+            std::vector<std::vector<int>> byres(32);
             for (int i = off[q * 8 + w]; i < off[q * 8 + w + 1]; i++)
-                byres[v[i].second & 63].push_back(v[i].second);
+                byres[wpos((uint32_t)v[i].second) & 31u].push_back(
+                    v[i].second);
             for (size_t k = 0;; k++) {
                 bool any = false;
-                for (int r = 0; r < 64; r++)
+                for (int r = 0; r < 32; r++)
                     if (k < byres[r].size()) {
                         ball.push_back((uint16_t)(byres[r][k] | (w << 12)));
                         any = true;
