@@ -1,10 +1,16 @@
-"""The batched workload at its full size against the oracle.
+"""The batched and served workloads at their full size against the oracle.
 
 The batched configuration is 256 instances of pmsgen.batched(seed=7):
 (l,d) uniform in {(9,2),(11,3),(13,4),(15,5)}, n in [10,40], m in
-[300,1000]. tests/golden/make_golden.py stored, from the oracle (O1) alone,
-the exact motif set of every instance: its size, the hash of its codes and,
-when short, the codes. Every instance is compared.
+[300,1000]. The served configuration is the 2000 requests of
+pmsgen.served(seed=11): (9,2) to (19,7), n = 20, m in [400,800].
+tests/golden/make_golden.py stored, from the oracle (O1) alone, the exact
+motif set of every batched instance, of every served request with l <= 13
+and of a seeded 10% sample of the (15,5) requests (then of the (17,6)
+ones): its size, the hash of its codes and, when short, the codes. Every
+stored instance is compared; served requests without a stored set are
+checked code by code with the direct motif check (Definition 5) and must
+hold the plant.
 """
 import hashlib
 import os
@@ -13,6 +19,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import paper_2403_00306_amd as pms
 import pmsgen
 
@@ -76,3 +83,44 @@ def test_batched_config_all_256_vs_oracle():
         check_against(got[i], gold[i], x, "batched instance %d" % i)
         np.testing.assert_array_equal(got[i], again[i])
         assert plant_code(x) in set(int(v) for v in got[i])
+
+
+def test_served_config_vs_oracle():
+    reqs = pmsgen.served(seed=11, count=2000)
+    gold = read_sets("served_seed11.txt")
+    by_ld = {}
+    for r in reqs:
+        by_ld.setdefault((r.inst.l, r.inst.d), []).append(r.index)
+    # coverage: every request with l <= 13 and at least 10% of the (15,5)
+    # ones; stored (17,6) sets are compared too
+    for ld, idx in by_ld.items():
+        have = sum(1 for i in idx if i in gold)
+        if ld[0] <= 13:
+            assert have == len(idx), (ld, have, len(idx))
+        elif ld == (15, 5):
+            assert have * 10 >= len(idx), (ld, have, len(idx))
+    say("served config: 2000 requests, %d with oracle sets" % len(gold))
+    with pms.Context(serve_queue=4096) as c:
+        tickets = [c.submit(r.inst.seqs, r.inst.n, r.inst.m, r.inst.l,
+                            r.inst.d) for r in reqs]
+        res = [c.wait(t, 300000) for t in tickets]
+        st = c.serve_stats()
+        for t in tickets:
+            c.release(t)
+    assert st["completed"] == len(reqs) and st["max_inflight"] > 1
+    checked = 0
+    for r, got in zip(reqs, res):
+        assert got is not None
+        x = r.inst
+        if r.index in gold:
+            check_against(got, gold[r.index], x, "request %d" % r.index)
+            checked += 1
+        else:
+            # (15,5)..(19,7) without a stored set: every code is a motif
+            # (direct check) and the plant is there
+            for v in got:
+                assert oracle.is_motif(x.seqs, x.n, x.m, x.l, x.d, int(v)), \
+                    (r.index, int(v))
+        assert plant_code(x) in set(int(v) for v in got), r.index
+    say("served: %d of %d requests compared with oracle sets" %
+        (checked, len(reqs)))
