@@ -66,17 +66,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# threads the oracle may use: the host's cores, at most the CPU share one
-# GPU's process is given on a shared node (16), and at most OMP_NUM_THREADS
-HOST_SHARE = 16
+def usable_cpus() -> int:
+    """CPUs this process may run on (its affinity mask)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
 
 
 def host_threads() -> int:
-    n = os.cpu_count() or 1
+    """Threads the oracle runs on: every CPU this process may use, at most
+    OMP_NUM_THREADS when that is set."""
+    n = usable_cpus()
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         n = min(n, int(env))
-    return max(1, min(n, HOST_SHARE))
+    return max(1, n)
 
 
 def cpu_model() -> str:
@@ -167,9 +172,9 @@ def cpu_baseline(inst, target_s: float = 12.0) -> dict:
     t = time.perf_counter() - t0
     return {"value": h / t, "unit": "Hamming tests/s", "cores": threads,
             "kind": "oracle", "cpu_model": cpu_model(),
-            "host_cpus": os.cpu_count(),
-            "threads_rule": "min(host CPUs, OMP_NUM_THREADS, %d: the CPU "
-                            "share of one GPU's process)" % HOST_SHARE,
+            "host_cpus": os.cpu_count(), "usable_cpus": usable_cpus(),
+            "threads_rule": "every CPU in the process's affinity mask, at "
+                            "most OMP_NUM_THREADS when set",
             "sample": "sample-driven oracle over the first %d of %d reference "
                       "l-mers of s_1 (same instance), %.1f s, %d tests"
                       % (k, L, t, h)}
