@@ -364,11 +364,14 @@ int pms_last_hcanon_per_ref(const pms_ctx *ctx, uint64_t *out, size_t n_refs);
 
 /*
  * Autotuner. Times every tile configuration (suffix length, survivor
- * threshold) of the tiled kernel on a synthetic instance shaped like
- * (n, m, l, d), keeps the fastest, and stores it in the context's tuning
- * table (and tune_cache file, if set) under the key (l, d, n-bucket,
- * m-bucket). Every configuration gives the same motif set; only speed
- * differs. *best_s / *best_t receive the choice (may be NULL).
+ * threshold and, for tiles of at least 4^7 codes unless
+ * pms_options.tile_threads fixes it, the workgroup size 256 or 512) of the
+ * tiled kernel on a synthetic planted instance shaped like (n, m, l, d),
+ * keeps the fastest, and stores it in the context's tuning table (and
+ * tune_cache file, if set) under the key (l, d, n-bucket, m-bucket). Every
+ * configuration gives the same motif set; only speed differs. *best_s /
+ * *best_t receive the suffix and threshold chosen (may be NULL); the
+ * workgroup size in effect shows in pms_last_stats' tile_threads.
  */
 int pms_autotune(pms_ctx *ctx, int n, int m, int l, int d, int *best_s,
                  int *best_t);

@@ -265,7 +265,7 @@ void pms_ctx::release(DevBuf &b)
     b.bytes = 0;
 }
 
-std::pair<int, int> pms_ctx::tile_config(int n, int m, int l, int d)
+TileCfg pms_ctx::tile_config(int n, int m, int l, int d)
 {
     std::lock_guard<std::mutex> g(tune_mu);
     auto o = override_cfg.find({l, d});
@@ -274,15 +274,16 @@ std::pair<int, int> pms_ctx::tile_config(int n, int m, int l, int d)
     auto t = tune.find(tune_key(l, d, n, m));
     if (t != tune.end())
         return t->second;
-    return {default_suffix(l), kDefaultSurv};
+    return {default_suffix(l), kDefaultSurv, 0};
 }
 
 Plan pms_ctx::plan(int n, int m, int l, int d, int forced)
 {
     Plan p{};
-    auto cfg = tile_config(n, m, l, d);
-    p.s = std::min(cfg.first, l);
-    p.surv_t = std::max(1, std::min(cfg.second, kSurvMax));
+    const TileCfg cfg = tile_config(n, m, l, d);
+    p.s = std::min(cfg.s, l);
+    p.surv_t = std::max(1, std::min(cfg.surv_t, kSurvMax));
+    p.tpb = cfg.tpb;
     p.ntiles = (l >= 3 && p.s >= 3) ? pow4(l - p.s) : 0;
     cost_model(n, m, l, d, p.s, p.surv_t, p.cost_filter, p.cost_tiled);
     if (forced == PMS_PATH_FILTER || forced == PMS_PATH_TILED ||
@@ -659,8 +660,7 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
             // tiles of 4^8 or 4^9 codes on the plain path: the 512-thread
             // kernel (twice the waves per CU in flight); it loses on the
             // smaller tiles (fewer words per thread than lanes can hide)
-            const bool wide =
-                !quorum && pick_wide(c, P.s >= kWideMinSuffix);
+            const bool wide = !quorum && pick_wide(c, P);
             const int tgrid =
                 grid_for(c, wide ? c->tiled_wide_bpc : c->tiled_bpc);
             // sibling tiles share one string order: items of kOrderReuse
@@ -1168,7 +1168,7 @@ int pms_set_tile_config(pms_ctx *c, int l, int d, int s, int surv_t)
         surv_t > kSurvMax)
         return c->fail(PMS_EINVAL, "tile config s=%d surv_t=%d out of range "
                        "(3<=s<=min(9,l), 1<=surv_t<=%d)", s, surv_t, kSurvMax);
-    c->override_cfg[{l, d}] = {s, surv_t};
+    c->override_cfg[{l, d}] = {s, surv_t, 0};
     return PMS_OK;
 }
 

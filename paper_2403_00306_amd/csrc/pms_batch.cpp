@@ -20,7 +20,7 @@ namespace {
 
 struct Member {
     int idx;
-    int n, m, l, d, s, surv_t;
+    int n, m, l, d, s, surv_t, tpb;
     uint64_t ntiles, tile_base;
     double cost;
     InstLayout lay;
@@ -77,6 +77,7 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         b.d = x.d;
         b.s = P.s;
         b.surv_t = P.surv_t;
+        b.tpb = P.tpb;
         b.ntiles = P.ntiles;
         b.cost = P.cost_tiled;
         mem.push_back(b);
@@ -117,11 +118,12 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         double total_cost = 0, wide_cost = 0;
         for (auto &b : mem) {
             total_cost += b.cost;
-            if (b.s >= kWideMinSuffix)
+            if (b.tpb ? b.tpb == 512 : b.s >= kWideMinSuffix)
                 wide_cost += b.cost;
         }
-        // the 512-thread tile kernel when most of the work is in tiles of
-        // at least 4^8 codes (faster there, slower on smaller tiles)
+        // the 512-thread tile kernel when most of the work is in instances
+        // that want it: tuned so, or untuned with tiles of at least 4^8
+        // codes (faster there, slower on smaller tiles)
         const bool wide = pick_wide(c, wide_cost >= 0.5 * total_cost);
         const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
         const double slots = (double)std::max(1, c->n_cu * tbpc);

@@ -55,10 +55,19 @@ InstDev make_desc(char *base, const InstLayout &o, const uint8_t *seqs,
                   int n, int m, int l, int d, int s, int surv_t,
                   uint64_t ntiles, uint64_t heap_cap);
 
+// Tile shape of the tiled kernel: suffix bases s (4^s codes per tile), the
+// survivor threshold, and the workgroup size (256 or 512; 0: automatic).
+struct TileCfg {
+    int s;
+    int surv_t;
+    int tpb;
+};
+
 struct Plan {
     int path;     // PMS_PATH_FILTER / PMS_PATH_TILED / PMS_PATH_BITSET
     int s;        // tile suffix bases
     int surv_t;   // survivor threshold of the tiled filter stage
+    int tpb;      // tile kernel workgroup size, 0: automatic
     uint64_t ntiles;
     double cost_filter, cost_tiled;
 };
@@ -110,8 +119,8 @@ struct pms_ctx {
     unsigned long long *pinned_hc = nullptr;   // per-reference counts
 
     std::mutex tune_mu;
-    std::map<uint64_t, std::pair<int, int>> tune;
-    std::map<std::pair<int, int>, std::pair<int, int>> override_cfg;
+    std::map<uint64_t, pms::TileCfg> tune;
+    std::map<std::pair<int, int>, pms::TileCfg> override_cfg;
 
     // batch
     pms::DevBuf b_arena;
@@ -135,7 +144,7 @@ struct pms_ctx {
         __attribute__((format(printf, 3, 4)));
     int alloc(pms::DevBuf &b, size_t bytes);
     void release(pms::DevBuf &b);
-    std::pair<int, int> tile_config(int n, int m, int l, int d);
+    pms::TileCfg tile_config(int n, int m, int l, int d);
     pms::Plan plan(int n, int m, int l, int d, int forced);
 };
 
@@ -155,6 +164,15 @@ inline bool pick_wide(const pms_ctx *c, bool automatic)
 {
     return c->opt.tile_threads == 512 ||
            (c->opt.tile_threads == 0 && automatic);
+}
+
+// The same for one instance's plan: the caller's choice, else the tuned
+// size, else 512 for tiles of at least 4^kWideMinSuffix codes.
+inline bool pick_wide(const pms_ctx *c, const Plan &p)
+{
+    if (c->opt.tile_threads != 0 || p.tpb == 0)
+        return pick_wide(c, p.s >= kWideMinSuffix);
+    return p.tpb == 512;
 }
 // q = 0 (or q = n): plain PMS; 1 <= q < n: (l,d,q)-motifs (tiled path).
 // fixed != nullptr: work in that memory (tiled path, d_out_ext required),

@@ -92,7 +92,7 @@ struct Pool {
 
 struct Req {
     uint64_t ticket = 0;
-    int n = 0, m = 0, l = 0, d = 0, s = 0, surv_t = 0;
+    int n = 0, m = 0, l = 0, d = 0, s = 0, surv_t = 0, tpb = 0;
     uint64_t ntiles = 0, next_tile = 0, heap_cap = 0;
     double cost_per_tile = 0;
     std::vector<char> seqs;
@@ -340,15 +340,15 @@ int Server::plan_launch(int b, const std::vector<Req *> &act)
         const uint64_t took = t - r->next_tile;
         r->next_tile = t;
         Lb.planned += (double)took * r->cost_per_tile;
-        if (r->s >= kWideMinSuffix)
+        if (r->tpb ? r->tpb == 512 : r->s >= kWideMinSuffix)
             planned_wide += (double)took * r->cost_per_tile;
         if (r->next_tile >= r->ntiles)
             Lb.last.push_back(r);
     }
     if (ni == 0)
         return PMS_OK;
-    // the 512-thread tile kernel when most of this launch's work is in
-    // tiles of at least 4^8 codes
+    // the 512-thread tile kernel when most of this launch's work wants it
+    // (tuned so, or untuned with tiles of at least 4^8 codes)
     const bool wide = pick_wide(c, planned_wide >= 0.5 * Lb.planned);
     const int tbpc = wide ? c->tiled_wide_bpc : c->tiled_bpc;
     if (hipMemcpyAsync(d_items[b], hi, sizeof(WorkItem) * ni,
@@ -604,6 +604,7 @@ int pms_submit(pms_ctx *c, const pms_instance *in, uint64_t *ticket)
     r->d = in->d;
     r->s = P.s;
     r->surv_t = P.surv_t;
+    r->tpb = P.tpb;
     r->ntiles = P.ntiles;
     r->cost_per_tile = std::max(1.0, P.cost_tiled / (double)P.ntiles);
     r->heap_cap = std::max<uint64_t>(4096, P.ntiles / 16);

@@ -1,13 +1,15 @@
 // pms_tune.cpp -- autotuner for the tiled kernel's tile shape.
 //
 // The tile shape decides how the 4^l code space is cut (suffix length s:
-// 4^s codes per tile, 4^(l-s) tiles) and when a tile stops ANDing sphere
-// unions and starts filtering the codes it has left (surv_t). Neither
-// changes the motif set, only the split of work between marking, prefix
-// tests and Hamming tests. The tuner times every shape on a synthetic
-// uniform-DNA instance of the requested size, checks that every shape
-// returns the same set, and keeps the fastest per (l, d, n-bucket,
-// m-bucket).
+// 4^s codes per tile, 4^(l-s) tiles), when a tile stops ANDing sphere
+// unions and starts filtering the codes it has left (surv_t), and the
+// workgroup size of the tile kernel (256 or 512 threads). None changes the
+// motif set, only the split of work between marking, prefix tests and
+// Hamming tests and how it is spread over the chip. The tuner times every
+// shape on a synthetic planted instance of the requested size (a random
+// motif with d substitutions at a random offset of every string, as in the
+// planted problem of Sec. 1.2.5), checks that every shape returns the same
+// set, and keeps the fastest per (l, d, n-bucket, m-bucket).
 #include "pms_host.h"
 
 #include <algorithm>
@@ -26,11 +28,19 @@ void load_tune_cache(pms_ctx *c)
     FILE *f = fopen(c->tune_path.c_str(), "r");
     if (!f)
         return;
-    unsigned long long key;
-    int s, t;
-    while (fscanf(f, "%llx %d %d", &key, &s, &t) == 3)
+    // lines "key s surv_t tpb"
+    char line[128];
+    while (fgets(line, sizeof line, f)) {
+        unsigned long long key;
+        int s, t, tpb = 0;
+        const int k = sscanf(line, "%llx %d %d %d", &key, &s, &t, &tpb);
+        if (k < 3)
+            continue;
+        if (tpb != 256 && tpb != 512)
+            tpb = 0;
         if (s >= kMinSuffix && s <= kMaxSuffix && t >= 1 && t <= kSurvMax)
-            c->tune[key] = {s, t};
+            c->tune[key] = {s, t, tpb};
+    }
     fclose(f);
 }
 
@@ -43,8 +53,8 @@ static void save_tune_cache(pms_ctx *c)
     if (!f)
         return;
     for (auto &kv : c->tune)
-        fprintf(f, "%llx %d %d\n", (unsigned long long)kv.first,
-                kv.second.first, kv.second.second);
+        fprintf(f, "%llx %d %d %d\n", (unsigned long long)kv.first,
+                kv.second.s, kv.second.surv_t, kv.second.tpb);
     fclose(f);
     rename(tmp.c_str(), c->tune_path.c_str());
 }
@@ -61,23 +71,48 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
         return c->fail(PMS_EINVAL, "autotune: bad shape n=%d m=%d l=%d d=%d",
                        n, m, l, d);
     hipSetDevice(c->device);
-    // synthetic uniform DNA (tuning input only)
+    // synthetic planted instance (tuning input only): uniform DNA with a
+    // random motif, d bases of it changed, at a random offset of each string
     std::mt19937_64 rng(tune_key(l, d, n, m) ^ 0x5eed5eedull);
     std::vector<char> seqs((size_t)n * m);
     for (auto &ch : seqs)
         ch = "ACGT"[rng() & 3];
+    std::vector<int> motif(l);
+    for (auto &b : motif)
+        b = (int)(rng() & 3);
+    for (int i = 0; i < n; i++) {
+        std::vector<int> occ = motif;
+        std::vector<int> pos(l);
+        for (int j = 0; j < l; j++)
+            pos[j] = j;
+        for (int k = 0; k < d; k++) {   // d distinct positions, new bases
+            const int r = k + (int)(rng() % (uint64_t)(l - k));
+            std::swap(pos[k], pos[r]);
+            occ[pos[k]] = (occ[pos[k]] + 1 + (int)(rng() % 3)) & 3;
+        }
+        const int at = (int)(rng() % (uint64_t)(m - l + 1));
+        for (int j = 0; j < l; j++)
+            seqs[(size_t)i * m + at + j] = "ACGT"[occ[j]];
+    }
 
-    // tile suffixes around the default (more tiles vs longer tiles) and
-    // three survivor thresholds
-    std::vector<std::pair<int, int>> cand;
+    // tile suffixes around the default (more tiles vs longer tiles), three
+    // survivor thresholds, and both workgroup sizes where the tile holds at
+    // least 4^7 codes (unless the caller fixed the size)
+    std::vector<TileCfg> cand;
     const int s_def = default_suffix(l);
     const int s_hi = std::min(std::min(kMaxSuffix, l), s_def + 2);
     const int s_lo = std::max(kMinSuffix, std::max(l - kMaxTilePrefix, s_def - 2));
     for (int s = s_lo; s <= s_hi; s++)
-        for (int t : {32, 64, 96})
-            cand.push_back({s, t});
+        for (int t : {32, 64, 96}) {
+            if (c->opt.tile_threads != 0 || s < 7) {
+                cand.push_back({s, t, 0});
+                continue;
+            }
+            cand.push_back({s, t, 256});
+            cand.push_back({s, t, 512});
+        }
 
-    std::pair<int, int> saved;
+    TileCfg saved{};
     bool had_override;
     {
         std::lock_guard<std::mutex> g(c->tune_mu);
@@ -87,7 +122,7 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
             saved = it->second;
     }
     double best = 1e300;
-    std::pair<int, int> pick = cand.front();
+    TileCfg pick = cand.front();
     std::vector<uint64_t> ref, got;
     bool have_ref = false;
     int status = PMS_OK;
@@ -119,8 +154,8 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
                     have_ref = true;
                 } else if (got != ref) {
                     status = c->fail(PMS_EDEVICE, "autotune: tile shape s=%d "
-                                     "t=%d changed the motif set", cf.first,
-                                     cf.second);
+                                     "t=%d threads=%d changed the motif set",
+                                     cf.s, cf.surv_t, cf.tpb);
                     break;
                 }
             }
@@ -146,9 +181,9 @@ extern "C" int pms_autotune(pms_ctx *c, int n, int m, int l, int d,
     if (status != PMS_OK)
         return status;
     if (best_s)
-        *best_s = pick.first;
+        *best_s = pick.s;
     if (best_t)
-        *best_t = pick.second;
+        *best_t = pick.surv_t;
     return PMS_OK;
 }
 

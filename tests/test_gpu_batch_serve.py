@@ -283,7 +283,16 @@ def test_autotune_picks_a_valid_shape(tmp_path):
         assert 3 <= s <= 9 and 1 <= t <= 256
         np.testing.assert_array_equal(c.solve(x.seqs, 10, 300, 11, 3), want)
         assert c.stats()["tile_suffix"] == s
+        threads = c.stats()["tile_threads"]
+    # one line "key s surv_t threads" (threads 0: chosen by tile size)
+    fields = open(cache).read().split()
+    assert len(fields) == 4 and (int(fields[1]), int(fields[2])) == (s, t)
+    tpb = int(fields[3])
+    assert tpb in (0, 256, 512)
+    if tpb:
+        assert threads == tpb
     # the cache file carries the choice to a new context
     with pms.Context(tune_cache=cache) as c2:
-        c2.solve(x.seqs, 10, 300, 11, 3)
+        np.testing.assert_array_equal(c2.solve(x.seqs, 10, 300, 11, 3), want)
         assert c2.stats()["tile_suffix"] == s
+        assert c2.stats()["tile_threads"] == threads
