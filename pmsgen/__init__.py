@@ -152,6 +152,7 @@ PLAIN_CONFIGS = {
     "pms_9_2": (20, 600, 9, 2),
     "pms_13_4": (20, 600, 13, 4),
     "pms_17_6": (20, 600, 17, 6),
+    "pms_19_7": (20, 600, 19, 7),
 }
 
 BATCH_CLASSES = [(9, 2), (11, 3), (13, 4), (15, 5)]

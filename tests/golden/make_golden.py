@@ -113,7 +113,8 @@ THREADS = int(os.environ.get("GOLDEN_THREADS", "0"))   # 0 = every core
 # (17,6) seeds 1..5; more seeds of (9,2) and (13,4)
 LARGE = [("pms_9_2", 4), ("pms_9_2", 5), ("pms_13_4", 2), ("pms_13_4", 3),
          ("pms_13_4", 4), ("pms_13_4", 5), ("pms_17_6", 1), ("pms_17_6", 2),
-         ("pms_17_6", 3), ("pms_17_6", 4), ("pms_17_6", 5)]
+         ("pms_17_6", 3), ("pms_17_6", 4), ("pms_17_6", 5),
+         ("pms_19_7", 1)]
 
 
 def main_large():
