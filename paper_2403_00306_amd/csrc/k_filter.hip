@@ -25,6 +25,13 @@ namespace pms {
 
 constexpr int kFPer = 8;                    // candidates per thread
 constexpr int kFBlock = kTPB * kFPer;       // candidates per block step
+#ifndef PMS_FILTER_REFS
+#define PMS_FILTER_REFS 8
+#endif
+constexpr int kFilterRefs = PMS_FILTER_REFS;  // references per block
+constexpr int kFilterRefsMinMasks = 16 * (kFBlock / kFilterRefs);
+static_assert(kFBlock % kFilterRefs == 0 && kFilterRefs <= kFBlock + 2,
+              "filter block layout");
 
 __device__ __forceinline__ uint64_t binom(int n, int k)
 {
@@ -170,6 +177,13 @@ __device__ __forceinline__ int scan_string(const BRow yp, int L,
     return L;
 }
 
+// Candidate layout: with G = 1 a block takes kFBlock consecutive (x, e)
+// in reference-major order (x = offset of the reference l-mer in s_1, e =
+// index in Mask(l,d)); with G > 1 (large spheres) a block takes G
+// consecutive references times kFBlock/G consecutive masks, so that each
+// slice of the mask table is read once per G references instead of once
+// per reference.
+template <int G>
 __global__ __launch_bounds__(kTPB) void
 k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
          unsigned long long *next_block, uint64_t *heap,
@@ -185,7 +199,12 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
     const int L = I.L, d = I.d, l = I.l;
     const PlaneRow x_planes = planes_row(I.planes, 0);   // row 0 = s_1
     const uint64_t total = (uint64_t)L * nb;
-    const uint64_t nblocks = (total + kFBlock - 1) / kFBlock;
+    // G > 1: blocks of G references x E masks, mask chunks inner
+    constexpr uint32_t E = (uint32_t)(kFBlock / G);
+    const uint64_t nec = (nb + E - 1) / E;
+    const uint64_t nblocks =
+        G == 1 ? (total + kFBlock - 1) / kFBlock
+               : (uint64_t)((L + G - 1) / G) * nec;
 
     for (;;) {
         __syncthreads();
@@ -196,7 +215,9 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         if (b >= nblocks)
             break;
         const uint64_t f0 = b * kFBlock;
-        const uint32_t x_first = (uint32_t)(f0 / nb);
+        const uint32_t x_first =
+            G == 1 ? (uint32_t)(f0 / nb) : (uint32_t)(b / nec) * (uint32_t)G;
+        const uint64_t e_first = G == 1 ? 0 : (b % nec) * E;
         for (int i = tid; i < kFBlock + 2; i += kTPB)
             sh.hc[i] = 0;
 
@@ -206,12 +227,23 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         unsigned int live = 0;
 #pragma unroll
         for (int k = 0; k < kFPer; k++) {
-            const uint64_t f = f0 + (uint64_t)k * kTPB + tid;
+            const uint32_t i = (uint32_t)(k * kTPB + tid);
+            uint32_t x;
+            uint64_t e;
+            bool ok;
+            if constexpr (G == 1) {
+                const uint64_t f = f0 + i;
+                ok = f < total;
+                x = ok ? (uint32_t)(f / nb) : 0u;
+                e = f - (uint64_t)x * nb;
+            } else {
+                x = x_first + i / E;
+                e = e_first + i % E;
+                ok = x < (uint32_t)L && e < nb;
+            }
             c[k] = make_uint2(0, 0);
             ref[k] = 0;
-            if (f < total) {
-                const uint32_t x = (uint32_t)(f / nb);
-                const uint64_t e = f - (uint64_t)x * nb;
+            if (ok) {
                 const uint2 xp = x_planes[x];
                 const uint2 mu = masks[e];
                 c[k] = make_uint2(xp.x ^ mu.x, xp.y ^ mu.y);
@@ -221,7 +253,10 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         }
         __syncthreads();   // hc cleared
 
-        int nlive = (int)min<uint64_t>((uint64_t)kFBlock, total - f0);
+        // an upper bound on the live slots (with G > 1 the empty ones of a
+        // partial block are scattered; their live bits are clear)
+        int nlive = G == 1 ? (int)min<uint64_t>((uint64_t)kFBlock, total - f0)
+                           : kFBlock;
         for (int si = 1; si < I.n && nlive > 0; si++) {
             const BRow yp{(const __attribute__((address_space(1))) unsigned
                            long long *)(const void *)(I.planes +
@@ -326,7 +361,9 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
         // flush the per-reference test counts of this block
         if (hc_per_ref) {
             const uint64_t f1 = min(f0 + kFBlock, total);
-            const uint32_t x_last = (uint32_t)((f1 - 1) / nb);
+            const uint32_t x_last =
+                G == 1 ? (uint32_t)((f1 - 1) / nb)
+                       : min(x_first + (uint32_t)G, (uint32_t)L) - 1u;
             for (uint32_t x = x_first + tid; x <= x_last; x += kTPB)
                 if (sh.hc[x - x_first])
                     atomicAdd(&hc_per_ref[x],
@@ -344,9 +381,16 @@ hipError_t launch_filter(const InstDev *d_inst, const uint2 *masks,
                          unsigned long long *hc_per_ref,
                          unsigned long long *hexec, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(kTPB), 0, st, d_inst, masks,
-                       nb, next_block, heap, heap_top, heap_cap, hc_per_ref,
-                       hexec);
+    // references per block: 8 where the sphere is large enough that the
+    // blocks of 256 masks waste little at its end, else 1
+    if (nb >= (uint64_t)kFilterRefsMinMasks)
+        hipLaunchKernelGGL(k_filter<kFilterRefs>, dim3(grid), dim3(kTPB), 0,
+                           st, d_inst, masks, nb, next_block, heap, heap_top,
+                           heap_cap, hc_per_ref, hexec);
+    else
+        hipLaunchKernelGGL(k_filter<1>, dim3(grid), dim3(kTPB), 0, st, d_inst,
+                           masks, nb, next_block, heap, heap_top, heap_cap,
+                           hc_per_ref, hexec);
     return hipGetLastError();
 }
 
@@ -540,8 +584,8 @@ uint32_t filter_quorum_max_refs() { return kQRefMask; }
 int filter_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filter, kTPB, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_filter<kFilterRefs>, kTPB, 0) != hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;
