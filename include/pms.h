@@ -65,7 +65,10 @@ enum {
     PMS_PATH_BITSET = 2,  /* pattern-driven, memory-heavy: one bit per l-mer
                              of the 4^l space resident in device memory,
                              one pass per string ANDs in the union of the
-                             d-spheres of its l-mers (needs 4^l/8 bytes) */
+                             d-spheres of its l-mers, each 4^9-code tile
+                             taking the strings in its own order (needs
+                             4^l/8 bytes, plus about 9 + 5n bytes per
+                             tile for its order and liveness) */
     PMS_PATH_TILED = 3,   /* pattern-driven, tiled: the 4^l space split into
                              tiles held on chip; each tile ANDs the strings'
                              sphere unions until few codes are left, then
