@@ -112,8 +112,12 @@ __device__ __forceinline__ void scan_string(const PairJob &J, int i,
                                             const uint32_t *cl, bool *live,
                                             unsigned long long &hc)
 {
-    const c_u64 *row = (const c_u64 *)(const void *)(
-        J.planes + (size_t)i * J.L);
+    // vector loads of the wave-uniform l-mers (one address, broadcast):
+    // they complete in order, so the compiler waits for each step's l-mers
+    // one by one instead of for all of them at once, as it must for scalar
+    // loads
+    typedef const __attribute__((address_space(1))) unsigned long long g_u64;
+    g_u64 *row = (g_u64 *)(const void *)(J.planes + (size_t)i * J.L);
     // running minimum distance per candidate (two l-mers per v_min3); a
     // dead candidate starts at 0 so that it never holds the wave back
     uint32_t mind[kPairPer];
@@ -124,9 +128,10 @@ __device__ __forceinline__ void scan_string(const PairJob &J, int i,
     }
     const uint32_t dd = (uint32_t)J.d;
     int y0 = 0;
-    for (; y0 + 8 <= J.L; y0 += 8) {
+    // sixteen l-mers a step: enough tests per wait for their scalar loads
+    for (; y0 + 16 <= J.L; y0 += 16) {
 #pragma unroll
-        for (int yy = 0; yy < 8; yy += 2) {
+        for (int yy = 0; yy < 16; yy += 2) {
             const unsigned long long v0 = row[y0 + yy], v1 = row[y0 + yy + 1];
             const uint32_t h0 = (uint32_t)v0, l0 = (uint32_t)(v0 >> 32);
             const uint32_t h1 = (uint32_t)v1, l1 = (uint32_t)(v1 >> 32);
@@ -143,7 +148,7 @@ __device__ __forceinline__ void scan_string(const PairJob &J, int i,
         if (__all(done))
             break;
     }
-    if (y0 + 8 > J.L) {
+    if (y0 + 16 > J.L) {
         for (int yy = y0; yy < J.L; yy++) {
             const unsigned long long v = row[yy];
             const uint32_t vh = (uint32_t)v, vl = (uint32_t)(v >> 32);
@@ -158,54 +163,68 @@ __device__ __forceinline__ void scan_string(const PairJob &J, int i,
         live[u] &= mind[u] <= dd;
 }
 
-// Append the lanes' kept entries with one atomic per wave (lanes that are
-// not active in the wave do not take part).
-__device__ __forceinline__ unsigned long long
-wave_slot(bool keep, unsigned long long *count, unsigned long long &below)
-{
-    const unsigned long long m = __ballot(keep);
-    if (m == 0)
-        return ~0ull;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(m) - 1;
-    unsigned long long base = 0;
-    if (lane == leader)
-        base = atomicAdd(count, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader, 64);
-    below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    return base;
-}
-
-// Survivors of a stage: to the next queue, or (after the last stage) as
-// codes to the heap.
+// Survivors of the block (live slots of every thread) to the next queue, or
+// to the heap after the last string, with one atomic per block call: every
+// block appends to the same counter, and one atomic per wave and slot made
+// that counter the bottleneck of the whole path. Called by every thread of
+// the block (it holds two barriers).
 __device__ __forceinline__ void emit(const PairJob &J, bool last,
                                      const uint32_t *ch, const uint32_t *cl,
                                      const bool *live, const uint32_t *prt,
                                      uint2 *qout, uint16_t *qpout,
                                      unsigned long long *qcount)
 {
+    constexpr int kWaves = kTPB / 64;
+    __shared__ unsigned int s_wcnt[kWaves];
+    __shared__ unsigned long long s_wbase[kWaves];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned long long m[kPairPer];
+    unsigned int cnt = 0;
 #pragma unroll
     for (int u = 0; u < kPairPer; u++) {
-        unsigned long long below = 0;
-        const unsigned long long base =
-            wave_slot(live[u], last ? J.heap_top : qcount, below);
-        if (!live[u] || base == ~0ull)
-            continue;
-        const unsigned long long at = base + below;
-        if (last) {
-            uint64_t code = 0;
-            for (int p = 0; p < J.l; p++)
-                code = (code << 2) | (((ch[u] >> p) & 1u) << 1) |
-                       ((cl[u] >> p) & 1u);
-            if (at < J.heap_cap)
-                J.heap[at] = code;
-        } else if (at < J.qcap) {
-            qout[at] = make_uint2(ch[u], cl[u]);
-            qpout[at] = (uint16_t)prt[u];
-        } else {
-            atomicOr(J.overflow, 1u);
+        m[u] = __ballot(live[u]);
+        cnt += (unsigned int)__popcll(m[u]);
+    }
+    if (lane == 0)
+        s_wcnt[wid] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tot = 0;
+        for (int w = 0; w < kWaves; w++)
+            tot += s_wcnt[w];
+        unsigned long long base =
+            tot ? atomicAdd(last ? J.heap_top : qcount,
+                            (unsigned long long)tot)
+                : 0ull;
+        for (int w = 0; w < kWaves; w++) {
+            s_wbase[w] = base;
+            base += s_wcnt[w];
         }
+    }
+    __syncthreads();
+    const unsigned long long below_mask =
+        lane ? (~0ull >> (64 - lane)) : 0ull;
+    unsigned long long at0 = s_wbase[wid];
+#pragma unroll
+    for (int u = 0; u < kPairPer; u++) {
+        if (live[u]) {
+            const unsigned long long at =
+                at0 + (unsigned long long)__popcll(m[u] & below_mask);
+            if (last) {
+                uint64_t code = 0;
+                for (int p = 0; p < J.l; p++)
+                    code = (code << 2) | (((ch[u] >> p) & 1u) << 1) |
+                           ((cl[u] >> p) & 1u);
+                if (at < J.heap_cap)
+                    J.heap[at] = code;
+            } else if (at < J.qcap) {
+                qout[at] = make_uint2(ch[u], cl[u]);
+                qpout[at] = (uint16_t)prt[u];
+            } else {
+                atomicOr(J.overflow, 1u);
+            }
+        }
+        at0 += (unsigned long long)__popcll(m[u]);
     }
 }
 
@@ -229,17 +248,7 @@ k_pair_filter(PairJob J, unsigned long long it1, unsigned long long npairs)
             const unsigned long long it = atomicAdd(J.next, 1ull);
             s_item = it;
             // the pair whose chunk range holds the item
-            unsigned long long lo = 0, hi = npairs - 1;
-            if (it < it1) {
-                while (lo < hi) {
-                    const unsigned long long mid = (lo + hi + 1) / 2;
-                    if (J.item_pos[mid] <= it)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-            }
-            s_pair = lo;
+            s_pair = it < it1 ? J.item_pair[it] : 0ull;
         }
         __syncthreads();
         const unsigned long long it = s_item;
@@ -417,6 +426,27 @@ hipError_t launch_pair_queue(const PairJob &J, int i, const uint2 *qin,
 {
     hipLaunchKernelGGL(k_pair_queue, dim3(grid), dim3(kTPB), 0, st, J, i, qin,
                        qpin, qin_count, qout, qpout, qout_count);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kTPB) void
+k_pair_items(PairJob J, unsigned long long npairs, uint32_t *item_pair)
+{
+    for (unsigned long long p = (unsigned long long)blockIdx.x * kTPB +
+                                threadIdx.x;
+         p < npairs; p += (unsigned long long)gridDim.x * kTPB)
+        for (uint64_t it = J.item_pos[p]; it < J.item_pos[p + 1]; it++)
+            item_pair[it] = (uint32_t)p;
+}
+
+hipError_t launch_pair_items(const PairJob &J, unsigned long long npairs,
+                             uint32_t *item_pair, hipStream_t st)
+{
+    const unsigned long long blocks = (npairs + kTPB - 1) / kTPB;
+    hipLaunchKernelGGL(k_pair_items,
+                       dim3((unsigned)std::min<unsigned long long>(blocks,
+                                                                   65535)),
+                       dim3(kTPB), 0, st, J, npairs, item_pair);
     return hipGetLastError();
 }
 

@@ -237,6 +237,7 @@ struct PairJob {
     unsigned long long *npairs, *ncand, *next, *tests;
     unsigned long long pairs_cap;
     const uint64_t *item_pos;    // exclusive scan of chunks (npairs+1)
+    const uint32_t *item_pair;   // the pair of each work item
     uint64_t *heap;              // survivors (unordered, repeats possible)
     unsigned long long *heap_top;
     unsigned long long heap_cap;
@@ -254,6 +255,9 @@ struct PairJob {
 hipError_t launch_pair_partner(const uint2 *planes, int n, int L,
                                uint32_t *partner, hipStream_t st);
 hipError_t launch_pair_list(const PairJob &J, hipStream_t st);
+// item_pair[it] = the pair whose work items hold it, for every item
+hipError_t launch_pair_items(const PairJob &J, unsigned long long npairs,
+                             uint32_t *item_pair, hipStream_t st);
 // Candidates of the work items [*J.next, it1) against s_3, survivors to
 // q[0] (count in *J.qcount); then each later string with launch_pair_queue.
 hipError_t launch_pair_filter(const PairJob &J, unsigned long long it1,

@@ -156,6 +156,7 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     J.qcap = 0;
     J.pairs_cap = LL;
     J.item_pos = (const uint64_t *)(b + o_pos);
+    J.item_pair = nullptr;
     J.heap = I.heap;
     J.heap_top = I.heap_top;
     J.heap_cap = I.heap_cap;
@@ -174,6 +175,8 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     HIPCHK(c, hipMemcpyAsync(hp, cnt, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     const unsigned long long npairs = hp[0], ncand = hp[1];
+    if (npairs >= (1ull << 32))   // work items name their pair in 32 bits
+        return c->fail(PMS_ENOMEM, "pair path: %llu pairs", npairs);
     unsigned long long nitems = 0;
     if (npairs) {
         HIPCHK(c, launch_scan_u32(J.chunks, npairs, (uint64_t *)J.item_pos,
@@ -190,13 +193,19 @@ int pair_run(pms_ctx *c, const InstDev &I, hipStream_t st, uint64_t *found,
     const unsigned long long qcap = std::max<unsigned long long>(
         (unsigned long long)pair_chunk(),
         std::min<unsigned long long>(1ull << 26, ncand + pair_chunk()));
-    if ((rc = c->alloc(c->alive, 2 * qcap * (sizeof(uint2) + 2))))
+    // the two queues, then the pair of every work item
+    const size_t q_bytes = 2 * qcap * (sizeof(uint2) + 2);
+    if ((rc = c->alloc(c->alive, q_bytes + (nitems + 1) * 4)))
         return rc;
     J.q[0] = (uint2 *)c->alive.p;
     J.q[1] = J.q[0] + qcap;
     J.qp[0] = (uint16_t *)(J.q[1] + qcap);
     J.qp[1] = J.qp[0] + qcap;
     J.qcap = qcap;
+    uint32_t *item_pair = (uint32_t *)((char *)c->alive.p + q_bytes);
+    J.item_pair = item_pair;
+    if (npairs)
+        HIPCHK(c, launch_pair_items(J, npairs, item_pair, st));
     const unsigned long long per_batch = qcap / pair_chunk();
     const int grid = std::max(1, c->n_cu * c->pair_bpc);
     for (unsigned long long lo = 0; lo < nitems; lo += per_batch) {
