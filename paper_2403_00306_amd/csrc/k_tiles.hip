@@ -1199,6 +1199,7 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
     constexpr int kTPB = TPB;
     constexpr int kPer = kMaxWords / TPB;   // words of A per thread
     typedef const __attribute__((address_space(4))) uint32_t c_u32;
+    __shared__ uint32_t s_keep[8];          // live tiles of a chunk (<= 8)
     const InstDev I = uni_desc(*inst);
     const int tid = threadIdx.x;
     const int s = I.s, q = s - 3, pl = I.l - s;
@@ -1230,6 +1231,7 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
         if (ch >= nchunks)
             break;
         const uint64_t i1 = min((ch + 1) * chunk, nitems);
+        unsigned int nkeep = 0;   // thread 0: the chunk's live tiles so far
         for (uint64_t it = ch * chunk; it < i1; it++) {
             // the list entry through a scalar load: it does not wait for
             // the previous tile's stores
@@ -1303,8 +1305,15 @@ __device__ void bitset_pass(const InstDev *inst, int pass, const Tables &tb,
             if (tid == 0) {
                 alive[t] = (uint8_t)(any != 0);
                 if (any)
-                    list_out[atomicAdd(&cnt[2 * pass + 1], 1u)] = (uint32_t)t;
+                    s_keep[nkeep++] = (uint32_t)t;
             }
+        }
+        // the chunk's live tiles to the next pass's list with one atomic
+        // (every workgroup appends to the same counter)
+        if (tid == 0 && nkeep) {
+            const unsigned int at = atomicAdd(&cnt[2 * pass + 1], nkeep);
+            for (unsigned int k = 0; k < nkeep; k++)
+                list_out[at + k] = s_keep[k];
         }
     }
     if (tid == 0 && stats) {
