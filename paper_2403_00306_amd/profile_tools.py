@@ -64,7 +64,12 @@ def source_hash(kernel: str) -> str:
 
 
 def short(name: str) -> str:
+    """Kernel name without namespace, return type, template arguments or
+    parameter list ("void pms::k_filter<8>(...)" -> "k_filter")."""
     n = name.split("(")[0]
+    if n.startswith("void "):
+        n = n[len("void "):]
+    n = re.sub(r"<[^<>]*>", "", n)
     return n.replace("pms::", "")
 
 
