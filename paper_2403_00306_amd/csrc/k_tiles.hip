@@ -1161,9 +1161,9 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // Byte p[i] (i uniform) through a scalar load of its aligned 32-bit word:
 // scalar loads are waited on by their own counter, so this read does not
 // wait for the vector stores still in flight (the previous tile's A). The
-// buffer behind p must extend to the end of that word. Used for bytes that
-// this launch reads before any write to them (the previous pass's liveness)
-// or never writes (the string order).
+// buffer behind p must extend to the end of that word, and no launch that
+// reads it may write it (the scalar cache is not kept coherent with vector
+// stores): here, the per-tile string order.
 __device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, uint64_t i)
 {
     typedef const __attribute__((address_space(4))) uint32_t c_u32;
