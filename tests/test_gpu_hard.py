@@ -1,17 +1,17 @@
 """GPU: the harder instances of the thesis's Table 3.3, (19,7), (21,8) and
 (23,9) with n = 20, m = 600, on the tiled path.
 
-The oracle cannot recompute these sets whole in a test (one reference's
-sphere at (21,8) is 1.6e9 candidates), so: at (19,7) the tiled path must
-equal the sample-driven filter path (a different algorithm) code for code;
-at every size each reported code is checked against every string by the
+The oracle cannot recompute these sets in a test (one reference's sphere at
+(21,8) is 1.6e9 candidates), so tests/golden/make_golden.py stored them from
+the oracle beforehand: the whole (19,7) set (O1 over every reference, with
+its canonical Hamming-test count), which the tiled, memory-heavy bitset and
+sample-driven filter paths must each equal code for code; and at (19,7) and
+(21,8) the motifs derived from single reference l-mers of s_1 (the plant's
+offset and two seeded others), each such subset inside the GPU's set, with
+the filter path's per-reference canonical counts equal to the oracle's. At
+every size each reported code is checked against every string by the
 oracle's direct check (Definition 5), one code at a time, and the planted
-motif must be reported. Completeness: tests/golden/make_golden.py stored,
-from the oracle, the motifs derived from single reference l-mers of s_1
-(the plant's offset and two seeded others) at (19,7) and (21,8); each such
-subset must lie inside the GPU's set, and at (19,7) the filter path's
-canonical Hamming-test count of each of those references must equal the
-oracle's.
+motif must be reported.
 """
 import hashlib
 import os
@@ -77,16 +77,38 @@ def check_refs(l, d, got):
     return refs
 
 
-def test_hard_19_7_paths_agree():
+def stored_whole(name, seed):
+    """(fields, codes) of a whole motif set stored by make_golden.py."""
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "%s_seed%d.txt" % (name, seed))
+    kv = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = [t.strip() for t in line.split("=", 1)]
+            kv[k] = v
+    codes = [int(x) for x in kv["motifs"].split(",") if x]
+    assert len(codes) == int(kv["count"])
+    return kv, codes
+
+
+def test_hard_19_7_whole_set():
     inst = pmsgen.planted(1, 20, 600, 19, 7)
+    kv, want = stored_whole("pms_19_7", 1)
+    assert kv["input_sha256"] == hashlib.sha256(inst.seqs).hexdigest()
     say("hard (19,7) tiled")
     with pms.Context(path=pms.PATH_TILED) as c:
         tiled = c.solve(inst.seqs, 20, 600, 19, 7)
+    assert [int(v) for v in tiled] == want
+    say("hard (19,7) bitset, 4^19 bits")
+    with pms.Context(path=pms.PATH_BITSET) as c:
+        bits = c.solve(inst.seqs, 20, 600, 19, 7)
+    assert [int(v) for v in bits] == want
     say("hard (19,7) filter")
     with pms.Context(path=pms.PATH_FILTER) as c:
         filt = c.solve(inst.seqs, 20, 600, 19, 7)
+        assert c.stats()["hcanon"] == int(kv["hcanon"])
         per = c.hcanon_per_ref(600 - 19 + 1)
-    assert list(tiled) == list(filt)
+    assert [int(v) for v in filt] == want
     check(inst, tiled)
     for j, h, _ in check_refs(19, 7, tiled):
         assert int(per[j]) == h, j

@@ -322,6 +322,19 @@ def test_string_order_limit_vs_oracle(threads):
         np.testing.assert_array_equal(got, want, err_msg="n=%d" % n)
 
 
+def test_bitset_order_limit_vs_oracle():
+    # the memory-heavy path orders the strings per tile for n <= 64 and
+    # takes them in input order above; (16,6) at s = 9, 4^7 tiles of 4^9 bits
+    n_l, n_d, m = 16, 6, 30
+    for n in (64, 65):
+        seqs = mutated_copies(64 + n, n, m, 2, 1)
+        want = oracle_set(seqs, n, m, n_l, n_d)
+        say("bitset order limit n", n)
+        got, st = solve_path(pms.PATH_BITSET, seqs, n, m, n_l, n_d)
+        assert st["tile_suffix"] == 9
+        np.testing.assert_array_equal(got, want, err_msg="n=%d" % n)
+
+
 def test_many_strings_every_path():
     # hundreds of strings (n has no upper limit): near-copies of one random
     # string, one base redrawn in each; every exact path, and the quorum at
