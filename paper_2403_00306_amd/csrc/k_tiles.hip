@@ -1182,7 +1182,7 @@ __device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, uint64_t i)
 // clustered. Items are taken in chunks from a counter, sized from the
 // list's length so that every workgroup gets several. 256 threads: the 16
 // words of A per thread stay in registers without spills. With ord (n bytes
-// per tile, from k_bitset_order) pass p ANDs each tile's p-th string in its
+// per tile, from k_bitset_mass and k_bitset_rank) pass p ANDs each tile's p-th string in its
 // own order, else string I.order[p] on every tile.
 //
 // cnt[2p] is pass p's chunk counter, cnt[2p+1] the length of the list pass
