@@ -1181,9 +1181,10 @@ __device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, uint64_t i)
 // scans dead tiles and the work shares stay even when the live tiles are
 // clustered. Items are taken in chunks from a counter, sized from the
 // list's length so that every workgroup gets several. 256 threads: the 16
-// words of A per thread stay in registers without spills. With ord (n bytes
-// per tile, from k_bitset_mass and k_bitset_rank) pass p ANDs each tile's p-th string in its
-// own order, else string I.order[p] on every tile.
+// words of A per thread stay in registers without spills. With ord (n
+// bytes per tile, from k_bitset_mass and k_bitset_rank) pass p ANDs each
+// tile's p-th string in its own order, else string I.order[p] on every
+// tile.
 //
 // cnt[2p] is pass p's chunk counter, cnt[2p+1] the length of the list pass
 // p writes (lists[(p+1)&1]); all start at zero. kLoad is false for pass 0
