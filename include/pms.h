@@ -225,10 +225,13 @@ int pms_solve_alphabet_device(pms_ctx *ctx, const char *alphabet, int sigma,
                               int d, void *stream, uint64_t *d_out,
                               size_t cap, size_t *count);
 
-/* One instance of a batch or a serving request. seqs: n*m host bytes. */
+/* One instance of a batch. seqs: n*m host bytes. q: quorum of an
+ * (l,d,q)-motif search (1 <= q < n; see pms_solve_quorum), 0 or n for the
+ * plain (l,d) search. */
 typedef struct {
     const char *seqs;
     int n, m, l, d;
+    int q;
 } pms_instance;
 
 /* Result of one instance. motifs: ctx-owned, ascending; status: PMS_*. */
@@ -241,10 +244,12 @@ typedef struct {
 /*
  * Solve k independent instances of any sizes together: all of them run in
  * one persistent launch that drains a device work queue, replayed as a
- * captured HIP graph when the same batch shape repeats. out[i] receives
- * instance i's result (status PMS_EBASE / PMS_EINVAL for a bad instance;
- * the others still complete). Returns PMS_OK if every instance succeeded,
- * else the first failing status.
+ * captured HIP graph when the same batch shape repeats. Instances the
+ * tiled kernel does not suit, and quorum instances (1 <= q < n), are solved
+ * one by one after it, as pms_solve / pms_solve_quorum would. out[i]
+ * receives instance i's result (status PMS_EBASE / PMS_EINVAL for a bad
+ * instance, q outside 0..n included; the others still complete). Returns
+ * PMS_OK if every instance succeeded, else the first failing status.
  */
 int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
                     pms_result *out);
@@ -262,8 +267,10 @@ int pms_solve_batch(pms_ctx *ctx, const pms_instance *in, int k,
  * proportion to its size and load.
  * *ticket identifies the request. PMS_EBUSY if the waiting queue is full;
  * PMS_EINVAL for a bad shape, for a shape the tiled path does not suit
- * (l < 3, or more than 4^14 tiles; use pms_solve) and PMS_ENOMEM for a
- * request larger than the serving pool (all checked before queueing).
+ * (l < 3, or more than 4^14 tiles; use pms_solve), for a quorum request
+ * (in->q other than 0 or n; use pms_solve_quorum or pms_solve_batch), and
+ * PMS_ENOMEM for a request larger than the serving pool (all checked
+ * before queueing).
  * Bad bytes are found on the device: the result's status is PMS_EBASE.
  * While requests are in flight, do not call pms_solve* or pms_autotune on
  * the same context from another thread.

@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
 
 class CInstance(ctypes.Structure):
     _fields_ = [("seqs", ctypes.c_char_p), ("n", ctypes.c_int),
-                ("m", ctypes.c_int), ("l", ctypes.c_int), ("d", ctypes.c_int)]
+                ("m", ctypes.c_int), ("l", ctypes.c_int), ("d", ctypes.c_int),
+                ("q", ctypes.c_int)]
 
 
 class CResult(ctypes.Structure):
@@ -335,19 +336,22 @@ class Context:
 
     # -- batch -------------------------------------------------------------
     def solve_batch(self, instances) -> list:
-        """instances: iterable of (seqs, n, m, l, d) or objects with those
-        attributes. Returns a list of uint64 arrays (or PmsError objects for
+        """instances: iterable of (seqs, n, m, l, d[, q]) or objects with
+        those attributes (q, the quorum, optional: 0 or n for the plain
+        search). Returns a list of uint64 arrays (or PmsError objects for
         instances that failed)."""
         insts = []
         keep = []
         for x in instances:
             if isinstance(x, tuple):
-                seqs, n, m, l, d = x
+                seqs, n, m, l, d = x[:5]
+                q = x[5] if len(x) > 5 else 0
             else:
                 seqs, n, m, l, d = x.seqs, x.n, x.m, x.l, x.d
+                q = getattr(x, "q", 0)
             b = _as_bytes(seqs)
             keep.append(b)
-            insts.append(CInstance(b, n, m, l, d))
+            insts.append(CInstance(b, n, m, l, d, q))
         k = len(insts)
         arr = (CInstance * max(k, 1))(*insts)
         res = (CResult * max(k, 1))()

@@ -58,10 +58,17 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         out[i].status = PMS_OK;
         const pms_instance &x = in[i];
         int rc = x.seqs ? check_shape(x.n, x.m, x.l, x.d) : PMS_EINVAL;
+        if (!rc && (x.q < 0 || x.q > x.n))
+            rc = PMS_EINVAL;
         if (rc) {
             out[i].status = rc;
             if (!first_bad)
                 first_bad = rc;
+            continue;
+        }
+        // quorum instances run one by one on their own kernels
+        if (x.q > 0 && x.q < x.n) {
+            solo.push_back(i);
             continue;
         }
         Plan P = c->plan(x.n, x.m, x.l, x.d, PMS_PATH_AUTO);
@@ -390,13 +397,15 @@ int batch_core(pms_ctx *c, const pms_instance *in, int k, pms_result *out)
         S.graph_replayed = replay ? 1 : 0;
         break;
     }
-    // instances the tiled kernel does not suit run one by one
+    // instances the tiled kernel does not suit, and quorum instances, run
+    // one by one
     c->b_solo.assign(solo.size(), {});
     for (size_t q = 0; q < solo.size(); q++) {
         const int i = solo[q];
         SolveOut r{};
+        const int qi = (in[i].q > 0 && in[i].q < in[i].n) ? in[i].q : 0;
         int rc = solve_core(c, in[i].seqs, nullptr, in[i].n, in[i].m, in[i].l,
-                            in[i].d, st, nullptr, 0, PMS_PATH_AUTO, &r);
+                            in[i].d, st, nullptr, 0, PMS_PATH_AUTO, &r, qi);
         if (rc) {
             out[i].status = rc;
             if (!first_bad)

@@ -581,6 +581,10 @@ int pms_submit(pms_ctx *c, const pms_instance *in, uint64_t *ticket)
                        in->l, in->d);
     if (in->n > kMaxOrder)
         return c->fail(PMS_EINVAL, "serving: n=%d above %d", in->n, kMaxOrder);
+    if (in->q != 0 && in->q != in->n)
+        return c->fail(PMS_EINVAL, "serving runs plain (l,d) requests (q=%d "
+                       "of n=%d); use pms_solve_quorum or pms_solve_batch",
+                       in->q, in->n);
     Plan P = c->plan(in->n, in->m, in->l, in->d, PMS_PATH_TILED);
     if (P.path != PMS_PATH_TILED)
         return c->fail(PMS_EINVAL, "serving runs the tiled path, which does "

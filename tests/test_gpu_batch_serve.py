@@ -45,6 +45,48 @@ def test_batch_matches_oracle_and_alone():
         np.testing.assert_array_equal(alone[i], want)
 
 
+def test_batch_with_quorum_instances():
+    # quorum instances (1 <= q < n) in a batch run one by one on their own
+    # kernels; plain ones (q = 0 or q = n) in the batched launch; q outside
+    # 0..n is a bad instance that does not spoil the others
+    plain = mixed_instances(31, 6, [(9, 2), (8, 2)], (4, 10), (60, 200))
+    qx = [pmsgen.planted(40 + k, 10, 120, 9, 2) for k in range(3)]
+    items = [(x.seqs, x.n, x.m, x.l, x.d) for x in plain]
+    items[1] = items[1] + (plain[1].n,)          # q = n: plain search
+    items += [(x.seqs, x.n, x.m, x.l, x.d, q)
+              for x, q in zip(qx, (3, 7, 9))]
+    items.append((qx[0].seqs, 10, 120, 9, 2, 11))   # q > n
+    items.append((qx[0].seqs, 10, 120, 9, 2, -1))   # q < 0
+    say("batch with quorum instances")
+    with pms.Context() as c:
+        got = c.solve_batch(items)
+    for i, x in enumerate(plain):
+        want = oracle.o1(x.seqs, x.n, x.m, x.l, x.d)[0]
+        np.testing.assert_array_equal(got[i], want, err_msg="plain %d" % i)
+    for k, (x, q) in enumerate(zip(qx, (3, 7, 9))):
+        want = oracle.q1(x.seqs, x.n, x.m, x.l, x.d, q)
+        np.testing.assert_array_equal(got[len(plain) + k], want,
+                                      err_msg="quorum q=%d" % q)
+    for bad in got[-2:]:
+        assert isinstance(bad, pms.PmsError)
+        assert bad.status == pms.PMS_EINVAL
+
+
+def test_served_rejects_quorum_requests():
+    x = pmsgen.planted(5, 6, 80, 9, 2)
+    with pms.Context() as c:
+        inst = pms.CInstance(x.seqs, 6, 80, 9, 2, 3)
+        t = pms.ctypes.c_uint64(0)
+        rc = c._lib.pms_submit(c._h, pms.ctypes.byref(inst),
+                               pms.ctypes.byref(t))
+        assert rc == pms.PMS_EINVAL
+        inst.q = 6                                   # q = n: plain request
+        assert c._lib.pms_submit(c._h, pms.ctypes.byref(inst),
+                                 pms.ctypes.byref(t)) == pms.PMS_OK
+        np.testing.assert_array_equal(c.wait(int(t.value), 60000),
+                                      oracle.o1(x.seqs, 6, 80, 9, 2)[0])
+
+
 def test_batch_graph_replays_with_eager_work_between():
     # the first call captures the batch's graph, the next three replay it;
     # a plain solve (other kernels, a host synchronisation) runs between
