@@ -338,6 +338,12 @@ mark_string(const InstDev &I, int seq, uint32_t Phi, uint32_t Plo,
             // class leaves idle fall in a different wave each time
             const uint32_t rot = 64u * (uint32_t)r;
             if (bs > (uint32_t)kTPB / 2) {
+                // These waves issue their ORs back to back, with no wait;
+                // a raised issue priority keeps the LDS fed from them while
+                // the CU's other waves sit in latency-bound phases (listing,
+                // AND and count, survivor tests). Raised for the lane-group
+                // classes too, it slowed the small tiles of (13,4).
+                __builtin_amdgcn_s_setprio(1);
                 // Entry-parallel: lane owns entries e, e+kTPB, ... of the
                 // sphere and the wave walks the class's l-mers, 64 at a
                 // time: one LDS read per lane, then broadcast by readlane.
@@ -420,6 +426,7 @@ mark_string(const InstDev &I, int seq, uint32_t Phi, uint32_t Plo,
                     }
                 }
             } else {
+                __builtin_amdgcn_s_setprio(0);
                 // G = kTPB/bs groups of bs lanes: each lane owns one entry
                 // and its group walks every G-th l-mer of the class (the
                 // division by bs is a multiply by a host-made constant)
@@ -468,6 +475,7 @@ mark_string(const InstDev &I, int seq, uint32_t Phi, uint32_t Plo,
             }
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
     }
     return marks;
 }
