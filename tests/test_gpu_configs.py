@@ -6,11 +6,11 @@ The batched configuration is 256 instances of pmsgen.batched(seed=7):
 pmsgen.served(seed=11): (9,2) to (19,7), n = 20, m in [400,800].
 tests/golden/make_golden.py stored, from the oracle (O1) alone, the exact
 motif set of every batched instance, of every served request with l <= 13
-and of a seeded 10% sample of the (15,5) requests (then of the (17,6)
-ones): its size, the hash of its codes and, when short, the codes. Every
-stored instance is compared; served requests without a stored set are
-checked code by code with the direct motif check (Definition 5) and must
-hold the plant.
+and of a seeded 10% sample of the (15,5) and (17,6) requests (then of
+the (19,7) ones, as the oracle finishes them): its size, the hash of its
+codes and, when short, the codes. Every stored instance is compared;
+served requests without a stored set are checked code by code with the
+direct motif check (Definition 5) and must hold the plant.
 """
 import hashlib
 import os
@@ -92,12 +92,12 @@ def test_served_config_vs_oracle():
     for r in reqs:
         by_ld.setdefault((r.inst.l, r.inst.d), []).append(r.index)
     # coverage: every request with l <= 13 and at least 10% of the (15,5)
-    # ones; stored (17,6) sets are compared too
+    # and (17,6) ones; stored (19,7) sets are compared too
     for ld, idx in by_ld.items():
         have = sum(1 for i in idx if i in gold)
         if ld[0] <= 13:
             assert have == len(idx), (ld, have, len(idx))
-        elif ld == (15, 5):
+        elif ld in ((15, 5), (17, 6)):
             assert have * 10 >= len(idx), (ld, have, len(idx))
     say("served config: 2000 requests, %d with oracle sets" % len(gold))
     with pms.Context(serve_queue=4096) as c:
