@@ -97,6 +97,15 @@ def _load():
         lib.oracle_encode.argtypes = [ctypes.c_char_p, ctypes.c_longlong,
                                       ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_longlong)]
+        lib.oracle_o1_wide.restype = ctypes.c_int
+        lib.oracle_o1_wide.argtypes = [
+            ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p),
+            ctypes.POINTER(ctypes.c_size_t), u64p]
+        lib.oracle_is_motif_wide.restype = ctypes.c_int
+        lib.oracle_is_motif_wide.argtypes = [
+            ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         _lib = lib
     return _lib
@@ -243,6 +252,35 @@ def is_motif(seqs, n, m, l, d, code) -> bool:
     rc = _load().oracle_is_motif(_seq_bytes(seqs), n, m, l, d, int(code))
     if rc < 0:
         raise OracleError(rc, "oracle_is_motif")
+    return rc == 1
+
+
+def o1_wide(seqs, n, m, l, d, threads=0):
+    """W1, the sample-driven oracle for 1 <= l <= 64: (codes, H_canon), the
+    codes as Python ints (up to 128 bits), ascending."""
+    lib = _load()
+    buf = _seq_bytes(seqs)
+    assert len(buf) == n * m
+    out = ctypes.POINTER(ctypes.c_uint64)()
+    count = ctypes.c_size_t(0)
+    h = ctypes.c_uint64(0)
+    rc = lib.oracle_o1_wide(buf, n, m, l, d, threads, ctypes.byref(out),
+                            ctypes.byref(count), ctypes.byref(h))
+    if rc != OR_OK:
+        raise OracleError(rc, "oracle_o1_wide")
+    words = _take(out, 2 * count.value)
+    codes = [(int(words[2 * i]) << 64) | int(words[2 * i + 1])
+             for i in range(count.value)]
+    return codes, int(h.value)
+
+
+def is_motif_wide(seqs, n, m, l, d, code) -> bool:
+    code = int(code)
+    rc = _load().oracle_is_motif_wide(_seq_bytes(seqs), n, m, l, d,
+                                      (code >> 64) & (2**64 - 1),
+                                      code & (2**64 - 1))
+    if rc < 0:
+        raise OracleError(rc, "oracle_is_motif_wide")
     return rc == 1
 
 

@@ -56,6 +56,11 @@
  * in the alphabet string), with codes in base sigma, first letter in the
  * top digit, and character-by-character distances.
  *
+ * Long motifs (Sec. 3.3.1 stores an l-mer in ceil(l/32) words per group
+ * when it does not fit one): W1 is O1 for 1 <= l <= 64, with 128-bit codes
+ * (the same first-base-in-the-top-digit order) returned as a high and a low
+ * 64-bit word per motif.
+ *
  * O1 also counts the canonical number of Hamming tests, H_canon: for each
  * enumerated candidate (with multiplicity over references x), (m-l+1) times
  * the number of strings s_2..s_n examined, up to and including the first one
@@ -1209,6 +1214,265 @@ int oracle_s0(const char *seqs, const char *alphabet, int sigma, int n,
     rc = gather_out(&v, 1, 0, out, count);
     free(v.v);
     return rc;
+}
+
+/* ---- W1: sample-driven over 128-bit codes (1 <= l <= 64) -------------- */
+
+typedef unsigned __int128 u128;
+
+/* A growable vector of 128-bit codes. */
+typedef struct {
+    u128 *v;
+    size_t n, cap;
+    int oom;
+} vec128;
+
+static void wpush(vec128 *a, u128 x)
+{
+    if (a->oom)
+        return;
+    if (a->n == a->cap) {
+        size_t nc = a->cap ? 2 * a->cap : 256;
+        u128 *nv = (u128 *)realloc(a->v, nc * sizeof(u128));
+        if (!nv) {
+            a->oom = 1;
+            return;
+        }
+        a->v = nv;
+        a->cap = nc;
+    }
+    a->v[a->n++] = x;
+}
+
+static int cmp_u128(const void *a, const void *b)
+{
+    u128 x = *(const u128 *)a, y = *(const u128 *)b;
+    return (x > y) - (x < y);
+}
+
+/* l-mer b[0..l-1] -> 128-bit code, first base in the top digit. */
+static u128 lmer_code128(const unsigned char *b, int l)
+{
+    u128 c = 0;
+    for (int j = 0; j < l; j++)
+        c = (c << 2) | b[j];
+    return c;
+}
+
+/* Digits that differ between two packed codes, counted on both halves. */
+static inline int hamming_packed128(u128 a, u128 b)
+{
+    const uint64_t m = 0x5555555555555555ULL;
+    u128 v = a ^ b;
+    v = v | (v >> 1);
+    return __builtin_popcountll((uint64_t)v & m) +
+           __builtin_popcountll((uint64_t)(v >> 64) & m);
+}
+
+typedef struct {
+    const u128 *codes;          /* n rows of L codes */
+    const unsigned char *bases; /* row 0 base codes */
+    int n, L, l, d, nthreads, tid;
+    vec128 out;
+    uint64_t hcanon;
+} w1_job;
+
+/* As o1_test: s_2..s_n in input order, stop at the first string with no
+ * l-mer within distance d. */
+static int w1_test(const w1_job *J, u128 cand, int *examined)
+{
+    int e = 0;
+    for (int i = 1; i < J->n; i++) {
+        const u128 *row = J->codes + (size_t)i * J->L;
+        int hit = 0;
+        e++;
+        for (int j = 0; j < J->L && !hit; j++)
+            hit = hamming_packed128(cand, row[j]) <= J->d;
+        if (!hit) {
+            *examined = e;
+            return 0;
+        }
+    }
+    *examined = e;
+    return 1;
+}
+
+/* T_d(x) as in o1_ball, on 128-bit codes. */
+static void w1_ball(w1_job *J, const unsigned char *x, u128 cand, int from,
+                    int budget, uint64_t *h)
+{
+    int examined;
+    if (w1_test(J, cand, &examined))
+        wpush(&J->out, cand);
+    *h += (uint64_t)examined * (uint64_t)J->L;
+    if (budget == 0)
+        return;
+    for (int p = from; p < J->l; p++) {
+        int shift = 2 * (J->l - 1 - p);
+        for (int b = 0; b < 4; b++) {
+            if (b == x[p])
+                continue;
+            w1_ball(J, x, cand ^ ((u128)(x[p] ^ b) << shift), p + 1,
+                    budget - 1, h);
+        }
+    }
+}
+
+static void *w1_worker(void *arg)
+{
+    w1_job *J = (w1_job *)arg;
+    int lo = (int)((long long)J->L * J->tid / J->nthreads);
+    int hi = (int)((long long)J->L * (J->tid + 1) / J->nthreads);
+    for (int j = lo; j < hi; j++) {
+        const unsigned char *x = J->bases + j;
+        uint64_t h = 0;
+        w1_ball(J, x, lmer_code128(x, J->l), 0, J->d, &h);
+        J->hcanon += h;
+    }
+    return NULL;
+}
+
+static int check_args_wide(int n, int m, int l, int d)
+{
+    if (n < 1 || l < 1 || l > 64 || m < l || d < 0 || d >= l)
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+/*
+ * W1: R for 1 <= l <= 64. *out (free with oracle_free) receives 2*count
+ * words, motif i as out[2i] = bits 127..64 and out[2i+1] = bits 63..0 of its
+ * code, ascending, no repeats; *hcanon gets H_canon.
+ */
+int oracle_o1_wide(const char *seqs, int n, int m, int l, int d, int nthreads,
+                   uint64_t **out, size_t *count, uint64_t *hcanon)
+{
+    int rc = check_args_wide(n, m, l, d);
+    if (rc)
+        return rc;
+    int L = m - l + 1;
+    size_t total = (size_t)n * (size_t)m;
+    unsigned char *bases = (unsigned char *)malloc(total);
+    u128 *codes = (u128 *)malloc(sizeof(u128) * (size_t)n * L);
+    if (!bases || !codes) {
+        free(bases);
+        free(codes);
+        return OR_ENOMEM;
+    }
+    if (decode(seqs, total, bases) >= 0) {
+        free(bases);
+        free(codes);
+        return OR_EBASE;
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < L; j++)
+            codes[(size_t)i * L + j] =
+                lmer_code128(bases + (size_t)i * m + j, l);
+    int T = pick_threads(nthreads);
+    if (T > L)
+        T = L;
+    w1_job *jobs = (w1_job *)calloc((size_t)T, sizeof(w1_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(bases);
+        free(codes);
+        free(jobs);
+        free(th);
+        return OR_ENOMEM;
+    }
+    for (int t = 0; t < T; t++) {
+        w1_job *J = &jobs[t];
+        J->codes = codes;
+        J->bases = bases;
+        J->n = n;
+        J->L = L;
+        J->l = l;
+        J->d = d;
+        J->nthreads = T;
+        J->tid = t;
+    }
+    for (int t = 1; t < T; t++)
+        pthread_create(&th[t], NULL, w1_worker, &jobs[t]);
+    w1_worker(&jobs[0]);
+    for (int t = 1; t < T; t++)
+        pthread_join(th[t], NULL);
+    size_t tot = 0;
+    int oom = 0;
+    uint64_t h = 0;
+    for (int t = 0; t < T; t++) {
+        tot += jobs[t].out.n;
+        oom |= jobs[t].out.oom;
+        h += jobs[t].hcanon;
+    }
+    u128 *all = (u128 *)malloc(sizeof(u128) * (tot ? tot : 1));
+    uint64_t *res = (uint64_t *)malloc(2 * sizeof(uint64_t) * (tot ? tot : 1));
+    if (!all || !res || oom) {
+        free(res);
+        rc = OR_ENOMEM;
+    } else {
+        size_t w = 0;
+        for (int t = 0; t < T; t++) {
+            if (jobs[t].out.n)
+                memcpy(all + w, jobs[t].out.v, jobs[t].out.n * sizeof(u128));
+            w += jobs[t].out.n;
+        }
+        /* a set: ascending, repeats dropped */
+        if (tot)
+            qsort(all, tot, sizeof(u128), cmp_u128);
+        size_t u = 0;
+        for (size_t i = 0; i < tot; i++)
+            if (u == 0 || all[i] != all[u - 1])
+                all[u++] = all[i];
+        for (size_t i = 0; i < u; i++) {
+            res[2 * i] = (uint64_t)(all[i] >> 64);
+            res[2 * i + 1] = (uint64_t)all[i];
+        }
+        *out = res;
+        *count = u;
+        if (hcanon)
+            *hcanon = h;
+    }
+    free(all);
+    for (int t = 0; t < T; t++)
+        free(jobs[t].out.v);
+    free(jobs);
+    free(th);
+    free(bases);
+    free(codes);
+    return rc;
+}
+
+/* Definitions 4-5 for one 128-bit code (hi: bits 127..64, lo: bits 63..0),
+ * compared character by character: 1 = motif, 0 = not, negative = error. */
+int oracle_is_motif_wide(const char *seqs, int n, int m, int l, int d,
+                         uint64_t hi, uint64_t lo)
+{
+    int rc = check_args_wide(n, m, l, d);
+    if (rc)
+        return rc;
+    u128 code = ((u128)hi << 64) | lo;
+    if (l < 64 && (code >> (2 * l)) != 0)
+        return OR_EINVAL;
+    unsigned char M[64];
+    for (int j = 0; j < l; j++)
+        M[j] = (unsigned char)((code >> (2 * (l - 1 - j))) & 3);
+    for (int i = 0; i < n; i++) {
+        const char *s = seqs + (size_t)i * m;
+        int ok = 0;
+        for (int j = 0; j + l <= m && !ok; j++) {
+            int h = 0;
+            for (int k = 0; k < l; k++) {
+                int b = base_code((unsigned char)s[j + k]);
+                if (b < 0)
+                    return OR_EBASE;
+                h += (b != M[k]);
+            }
+            ok = h <= d;
+        }
+        if (!ok)
+            return 0;
+    }
+    return 1;
 }
 
 void oracle_free(void *p)
