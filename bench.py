@@ -35,6 +35,9 @@ OPS_MARK = 2.0
 # any-alphabet filter, per Hamming test on 5 bit planes: v_xor, four
 #   v_bitop3 (s0 | (s1 ^ s2)), v_bcnt and half a v_min3 = 6.5
 OPS_TEST_ALPHA = 6.5
+# long motifs (l up to 64), per Hamming test on two 64-bit planes: per
+#   32-bit half a v_xor, a v_bitop3 and a v_bcnt, then half a v_min = 6.5
+OPS_TEST_WIDE = 6.5
 # quorum path, per 64-code word per pass: the bit-sliced increment (XOR and
 # AND per counter plane, 5 planes); counters start at 31 - (n - q), so the
 # carry out of the top plane is the test and needs no compare
@@ -390,6 +393,36 @@ def protein_bench(pms, pmsgen, np) -> dict:
     return res
 
 
+def wide_bench(pms, pmsgen, np) -> dict:
+    """Long motifs: planted (40,4), n = 20, m = 600, seed 1, through the
+    128-bit-code path (one 64-bit word per bit plane); canonical Hamming
+    tests per second and its roofline."""
+    inst = pmsgen.planted(1, 20, 600, 40, 4)
+    plant = 0
+    for ch in inst.motif:
+        plant = 4 * plant + b"ACGT".index(ch)
+    with pms.Context(device=0) as c:
+        c.solve_wide(inst.seqs, 20, 600, 40, 4)
+        t0 = time.perf_counter()
+        got = c.solve_wide(inst.seqs, 20, 600, 40, 4)
+        wall = (time.perf_counter() - t0) * 1000.0
+        st = c.stats()
+    codes = set((int(h) << 64) | int(lo) for h, lo in got)
+    ops = st["hcanon"] * OPS_TEST_WIDE
+    log("wide (40,4): %.1f ms, %d motifs" % (wall, len(got)))
+    return {"workload": "planted (40,4), n=20, m=600, seed 1",
+            "solve_ms": wall, "kernel_ms": st["ms_main"],
+            "motifs": int(len(got)), "planted_found": plant in codes,
+            "hcanon": st["hcanon"],
+            "tests_per_s": st["hcanon"] / (st["ms_main"] / 1000.0),
+            "roofline": {"bound": "alu", "kernel": "k_wide_filter",
+                         "traffic": measured_traffic("k_wide_filter"),
+                         "achieved": ops / (st["ms_main"] / 1000.0) / 1e12,
+                         "peak": PEAK_ALU_OPS / 1e12, "unit": "TOP/s",
+                         "frac": ops / (st["ms_main"] / 1000.0)
+                         / PEAK_ALU_OPS}}
+
+
 def pair_bench(pms, inst, np) -> dict:
     """The pair-based sample-driven path (Observation 3.3) on the timed
     (17,6) instance: compatible pairs, candidates, tests and its roofline."""
@@ -628,6 +661,7 @@ def main():
         extra["quorum"] = quorum_bench(pms, pmsgen, np, torch, dev)
         extra["pair_path"] = pair_bench(pms, inst, np)
         extra["protein"] = protein_bench(pms, pmsgen, np)
+        extra["wide"] = wide_bench(pms, pmsgen, np)
         if not args.no_hard:
             extra["hard"] = hard_bench(pms, pmsgen, np)
     if not args.no_batch:

@@ -21,7 +21,8 @@
  * 1 <= q <= n (Definition 5); pms_solve_alphabet solves the same problem
  * over another alphabet of 2..32 letters (codes in base sigma, see there);
  * PMS_PATH_PAIR (an option of the context) computes the plain set from
- * pairs of l-mers of s_1 and s_2 (Observation 3.3).
+ * pairs of l-mers of s_1 and s_2 (Observation 3.3); pms_solve_wide takes
+ * motifs up to l = 64 (128-bit codes, see there).
  *
  * Ownership. Inputs are copied before a call returns (pms_submit included),
  * so the caller may free them at once. Result arrays belong to the context
@@ -224,6 +225,30 @@ int pms_solve_alphabet_device(pms_ctx *ctx, const char *alphabet, int sigma,
                               const uint8_t *d_seqs, int n, int m, int l,
                               int d, void *stream, uint64_t *d_out,
                               size_t cap, size_t *count);
+
+/*
+ * Long motifs, 1 <= l <= 64 (Sec. 3.3.1 keeps an l-mer that one word cannot
+ * hold in ceil(l/32) words per group). The problem is pms_solve's; a code
+ * takes up to 128 bits and is returned as two uint64 words, high word first:
+ * motif i is (*motifs)[2i] = bits 127..64 and (*motifs)[2i+1] = bits 63..0
+ * of sum_j b(M[j]) * 4^(l-1-j). Motifs ascend by that 128-bit value;
+ * *count counts motifs (2 * *count words). Runs the sample-driven filter
+ * with one 64-bit word per bit plane (candidates from the spheres of s_1's
+ * l-mers, strings tested in order with early exit, each motif kept from the
+ * first l-mer of s_1 within d of it), then sorts on the device. The words
+ * belong to the context as for pms_solve. Errors as pms_solve, with the
+ * domain 1 <= l <= 64; PMS_EINVAL also for a sphere beyond 2^62 candidates
+ * or 2^22 position sets. For l <= 32 the low words are pms_solve's codes.
+ */
+int pms_solve_wide(pms_ctx *ctx, const char *seqs, int n, int m, int l,
+                   int d, const uint64_t **motifs, size_t *count);
+
+/* pms_solve_wide with input and output in device memory, as
+ * pms_solve_device: d_out holds 2 * cap words (cap motifs); PMS_ENOMEM with
+ * *count = the number of motifs when cap is too small. */
+int pms_solve_wide_device(pms_ctx *ctx, const uint8_t *d_seqs, int n, int m,
+                          int l, int d, void *stream, uint64_t *d_out,
+                          size_t cap, size_t *count);
 
 /* One instance of a batch. seqs: n*m host bytes. q: quorum of an
  * (l,d,q)-motif search (1 <= q < n; see pms_solve_quorum), 0 or n for the

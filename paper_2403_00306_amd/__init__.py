@@ -118,6 +118,10 @@ def load_library(path: str = LIB_PATH):
                                    i, i, i, i, P(P(ctypes.c_uint64)), P(sz)]),
         "pms_solve_alphabet_device": (i, [vp, ctypes.c_char_p, i, vp, i, i,
                                           i, i, vp, vp, sz, P(sz)]),
+        "pms_solve_wide": (i, [vp, ctypes.c_char_p, i, i, i, i,
+                               P(P(ctypes.c_uint64)), P(sz)]),
+        "pms_solve_wide_device": (i, [vp, vp, i, i, i, i, vp, vp, sz,
+                                      P(sz)]),
         "pms_solve_batch": (i, [vp, P(CInstance), i, P(CResult)]),
         "pms_submit": (i, [vp, P(CInstance), P(u64)]),
         "pms_poll": (i, [vp, u64, P(CResult)]),
@@ -325,6 +329,39 @@ class Context:
         cnt = ctypes.c_size_t(0)
         rc = self._lib.pms_solve_alphabet_device(
             self._h, a, len(a), ctypes.c_void_p(d_seqs), n, m, l, d,
+            ctypes.c_void_p(stream), ctypes.c_void_p(d_out), cap,
+            ctypes.byref(cnt))
+        if rc == PMS_ENOMEM and cnt.value > cap:
+            err = PmsError(rc, self._lib.pms_last_error(self._h).decode())
+            err.needed = cnt.value
+            raise err
+        self._check(rc)
+        return cnt.value
+
+    def solve_wide(self, seqs, n: int, m: int, l: int, d: int) -> np.ndarray:
+        """Motifs of length up to 64: a (count, 2) uint64 array, row i the
+        high and low word of motif i's 128-bit code, ascending."""
+        buf = _as_bytes(seqs)
+        if len(buf) != n * m:
+            raise ValueError("seqs holds %d bytes, expected n*m=%d"
+                             % (len(buf), n * m))
+        ptr = ctypes.POINTER(ctypes.c_uint64)()
+        cnt = ctypes.c_size_t(0)
+        self._check(self._lib.pms_solve_wide(self._h, buf, n, m, l, d,
+                                             ctypes.byref(ptr),
+                                             ctypes.byref(cnt)))
+        if cnt.value == 0:
+            return np.zeros((0, 2), dtype=np.uint64)
+        return np.ctypeslib.as_array(
+            ptr, shape=(2 * cnt.value,)).copy().reshape(cnt.value, 2)
+
+    def solve_wide_device(self, d_seqs: int, n: int, m: int, l: int, d: int,
+                          d_out: int, cap: int, stream: int = 0) -> int:
+        """Device-resident solve_wide: d_out holds 2*cap uint64 words;
+        returns the number of motifs."""
+        cnt = ctypes.c_size_t(0)
+        rc = self._lib.pms_solve_wide_device(
+            self._h, ctypes.c_void_p(d_seqs), n, m, l, d,
             ctypes.c_void_p(stream), ctypes.c_void_p(d_out), cap,
             ctypes.byref(cnt))
         if rc == PMS_ENOMEM and cnt.value > cap:

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libpms.so")
 SOURCES = ["k_index.hip", "k_tiles.hip", "k_filter.hip", "k_scan.hip",
            "k_alpha.hip", "k_pair.hip", "pms_api.cpp", "pms_batch.cpp",
            "pms_serve.cpp", "pms_tune.cpp", "pms_alpha.cpp", "pms_pair.cpp",
-           "pms_noalloc.hip"]
+           "pms_noalloc.hip", "k_wide.hip", "pms_wide.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-result",

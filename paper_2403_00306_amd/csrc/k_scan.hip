@@ -7,7 +7,7 @@
 // tile its final position, and an ordered gather moves the blocks there.
 // The sample-driven filter path produces its survivors in no particular
 // order, so it sorts them (LSD radix sort on device, 8 bits per pass).
-#include "pms_internal.h"
+#include "pms_wide.h"
 
 #include <algorithm>
 
@@ -239,19 +239,50 @@ hipError_t launch_ranges(const InstDev *d_insts, int ninst,
 }
 
 // ---- sorting --------------------------------------------------------------
+// Keys are 64-bit codes or, for long motifs, 128-bit codes (high word
+// first); SortKey gives the digit, the order and the padding of each.
 
-constexpr int kSmallSort = 4096;
+template <class K>
+struct SortKey;
 
-// Bitonic sort of n <= 4096 keys in one workgroup (padding with ~0).
-__global__ __launch_bounds__(kTPB) void k_sort_small(uint64_t *keys,
-                                                     uint64_t n)
+template <>
+struct SortKey<uint64_t> {
+    static constexpr int kSmall = 4096;   // one-workgroup sort up to this
+    __device__ static uint32_t digit(uint64_t k, int shift)
+    {
+        return (uint32_t)(k >> shift) & 255u;
+    }
+    __device__ static bool less(uint64_t a, uint64_t b) { return a < b; }
+    __device__ static uint64_t pad() { return ~0ull; }
+};
+
+template <>
+struct SortKey<W128> {
+    static constexpr int kSmall = 2048;   // 32 KiB of LDS
+    __device__ static uint32_t digit(const W128 &k, int shift)
+    {
+        return (uint32_t)(shift < 64 ? k.lo >> shift : k.hi >> (shift - 64)) &
+               255u;
+    }
+    __device__ static bool less(const W128 &a, const W128 &b)
+    {
+        return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+    }
+    __device__ static W128 pad() { return W128{~0ull, ~0ull}; }
+};
+
+// Bitonic sort of n <= SortKey<K>::kSmall keys in one workgroup (padding
+// sorts last).
+template <class K>
+__global__ __launch_bounds__(kTPB) void k_sort_small(K *keys, uint64_t n)
 {
-    __shared__ uint64_t a[kSmallSort];
+    typedef SortKey<K> S;
+    __shared__ K a[S::kSmall];
     int N = 1;
     while ((uint64_t)N < n)
         N <<= 1;
     for (int i = threadIdx.x; i < N; i += kTPB)
-        a[i] = (uint64_t)i < n ? keys[i] : ~0ull;
+        a[i] = (uint64_t)i < n ? keys[i] : S::pad();
     __syncthreads();
     for (int k = 2; k <= N; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -259,8 +290,8 @@ __global__ __launch_bounds__(kTPB) void k_sort_small(uint64_t *keys,
                 const int p = i ^ j;
                 if (p > i) {
                     const bool up = (i & k) == 0;
-                    const uint64_t x = a[i], y = a[p];
-                    if ((x > y) == up) {
+                    const K x = a[i], y = a[p];
+                    if (S::less(y, x) == up) {
                         a[i] = y;
                         a[p] = x;
                     }
@@ -274,9 +305,10 @@ __global__ __launch_bounds__(kTPB) void k_sort_small(uint64_t *keys,
 }
 
 // Per-block digit histograms, digit-major: hist[digit * nb + block].
-__global__ __launch_bounds__(kTPB) void k_rs_hist(const uint64_t *keys,
-                                                  uint64_t n, int shift,
-                                                  uint32_t *hist, uint64_t nb)
+template <class K>
+__global__ __launch_bounds__(kTPB) void k_rs_hist(const K *keys, uint64_t n,
+                                                  int shift, uint32_t *hist,
+                                                  uint64_t nb)
 {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
@@ -285,7 +317,7 @@ __global__ __launch_bounds__(kTPB) void k_rs_hist(const uint64_t *keys,
     for (int k = 0; k < kScanPer; k++) {
         const uint64_t i = base + (uint64_t)k * kTPB + threadIdx.x;
         if (i < n)
-            atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+            atomicAdd(&cnt[SortKey<K>::digit(keys[i], shift)], 1u);
     }
     __syncthreads();
     hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
@@ -294,9 +326,10 @@ __global__ __launch_bounds__(kTPB) void k_rs_hist(const uint64_t *keys,
 // Stable scatter: keys of a block keep their relative order within each
 // digit. Per round of 256 keys: peers with the same digit inside a wave are
 // found with 8 ballots; waves are ordered through per-wave digit counts.
+template <class K>
 __global__ __launch_bounds__(kTPB) void
-k_rs_scatter(const uint64_t *in, uint64_t *out, uint64_t n, int shift,
-             const uint64_t *offs, uint64_t nb)
+k_rs_scatter(const K *in, K *out, uint64_t n, int shift, const uint64_t *offs,
+             uint64_t nb)
 {
     __shared__ unsigned long long base[256];
     __shared__ uint32_t wcnt[kWaves][256];
@@ -309,8 +342,8 @@ k_rs_scatter(const uint64_t *in, uint64_t *out, uint64_t n, int shift,
     for (int k = 0; k < kScanPer; k++) {
         const uint64_t i = b0 + (uint64_t)k * kTPB + tid;
         const bool valid = i < n;
-        const uint64_t key = valid ? in[i] : 0ull;
-        const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+        const K key = valid ? in[i] : K{};
+        const uint32_t dig = SortKey<K>::digit(key, shift);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -345,52 +378,71 @@ k_rs_scatter(const uint64_t *in, uint64_t *out, uint64_t n, int shift,
 // scan scratch.
 static size_t pad64(size_t b) { return (b + 63) / 64 * 64 + 64; }
 
-size_t sort_scratch_bytes(uint64_t n)
+template <class K>
+static size_t sort_scratch(uint64_t n)
 {
     const uint64_t nb = (n + kScanTile - 1) / kScanTile;
     const uint64_t h = 256 * nb;
-    return pad64(sizeof(uint64_t) * n) + pad64(sizeof(uint32_t) * h) +
+    return pad64(sizeof(K) * n) + pad64(sizeof(uint32_t) * h) +
            pad64(sizeof(uint64_t) * (h + 1)) + scan_scratch_bytes(h);
 }
 
-hipError_t launch_sort_u64(uint64_t *keys, uint64_t n, int key_bits,
-                           void *scratch, hipStream_t st)
+template <class K>
+static hipError_t sort_keys(K *keys, uint64_t n, int key_bits, void *scratch,
+                            hipStream_t st)
 {
     if (n <= 1)
         return hipSuccess;
-    if (n <= (uint64_t)kSmallSort) {
-        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kTPB), 0, st, keys, n);
+    if (n <= (uint64_t)SortKey<K>::kSmall) {
+        hipLaunchKernelGGL(k_sort_small<K>, dim3(1), dim3(kTPB), 0, st, keys,
+                           n);
         return hipGetLastError();
     }
     const uint64_t nb = (n + kScanTile - 1) / kScanTile;
     const uint64_t h = 256 * nb;
     char *p = (char *)scratch;
-    uint64_t *tmp = (uint64_t *)p;
-    p += pad64(sizeof(uint64_t) * n);
+    K *tmp = (K *)p;
+    p += pad64(sizeof(K) * n);
     uint32_t *hist = (uint32_t *)p;
     p += pad64(sizeof(uint32_t) * h);
     uint64_t *offs = (uint64_t *)p;
     p += pad64(sizeof(uint64_t) * (h + 1));
     void *sscr = p;
-    uint64_t *src = keys, *dst = tmp;
+    K *src = keys, *dst = tmp;
     const int passes = (key_bits + 7) / 8;
     for (int ps = 0; ps < passes; ps++) {
         const int shift = 8 * ps;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kTPB), 0, st,
-                           src, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kTPB), 0,
+                           st, src, n, shift, hist, nb);
         hipError_t e = launch_scan_u32(hist, h, offs, sscr, st);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kTPB), 0,
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nb), dim3(kTPB), 0,
                            st, src, dst, n, shift, offs, nb);
-        uint64_t *t = src;
+        K *t = src;
         src = dst;
         dst = t;
     }
     if (src != keys)
-        return hipMemcpyAsync(keys, src, sizeof(uint64_t) * n,
+        return hipMemcpyAsync(keys, src, sizeof(K) * n,
                               hipMemcpyDeviceToDevice, st);
     return hipGetLastError();
+}
+
+size_t sort_scratch_bytes(uint64_t n) { return sort_scratch<uint64_t>(n); }
+
+hipError_t launch_sort_u64(uint64_t *keys, uint64_t n, int key_bits,
+                           void *scratch, hipStream_t st)
+{
+    return sort_keys<uint64_t>(keys, n, key_bits, scratch, st);
+}
+
+size_t sort_scratch_bytes_w128(uint64_t n) { return sort_scratch<W128>(n); }
+
+hipError_t launch_sort_w128(W128 *keys, uint64_t n, int key_bits,
+                            void *scratch, hipStream_t st)
+{
+    return sort_keys<W128>(keys, n, key_bits, scratch, st);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)

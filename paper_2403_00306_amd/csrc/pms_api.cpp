@@ -6,6 +6,7 @@
 // kernels on the context's stream and brings the ascending motif set back.
 // pms_serve.cpp holds the serving engine, pms_tune.cpp the autotuner.
 #include "pms_host.h"
+#include "pms_wide.h"
 
 #include <algorithm>
 #include <cmath>
@@ -928,6 +929,7 @@ int pms_create(pms_ctx **out, const pms_options *opt)
     c->tiled_q_bpc = tiled_quorum_blocks_per_cu();
     c->bitset_bpc = bitset_blocks_per_cu();
     c->alpha_bpc = alpha_blocks_per_cu();
+    c->wide_bpc = wide_blocks_per_cu();
     c->pair_bpc = pair_blocks_per_cu();
     c->filter_bpc = filter_blocks_per_cu();
     size_t freeb = 0, totb = 0;

@@ -99,7 +99,8 @@ struct pms_ctx {
     std::string tune_path;
     hipStream_t stream = nullptr;
     int n_cu = 0, tiled_bpc = 1, filter_bpc = 1, tiled_q_bpc = 1,
-        alpha_bpc = 1, pair_bpc = 1, tiled_wide_bpc = 1, bitset_bpc = 1;
+        alpha_bpc = 1, pair_bpc = 1, tiled_wide_bpc = 1, bitset_bpc = 1,
+        wide_bpc = 1;
     size_t budget = 0;
     std::atomic<size_t> held{0};
 

@@ -42,7 +42,8 @@ KERNEL_SOURCES = {"k_tiled": "csrc/k_tiles.hip", "k_bitset_pass": "csrc/k_tiles.
                   "k_tiled_quorum": "csrc/k_tiles.hip",
                   "k_alpha_filter": "csrc/k_alpha.hip",
                   "k_pair_filter": "csrc/k_pair.hip",
-                  "k_filter": "csrc/k_filter.hip"}
+                  "k_filter": "csrc/k_filter.hip",
+                  "k_wide_filter": "csrc/k_wide.hip"}
 
 
 def _code_text(path: str) -> str:

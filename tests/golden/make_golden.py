@@ -4,7 +4,7 @@ Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
 on inputs from the seeded generator; nothing here touches the GPU library.
 Run from the repository root:  python tests/golden/make_golden.py
 (add "quorum" or "protein" to write only those files; "large", "batched",
-"served" or "hard" write the long-running sets below, which take hours of
+"served", "hard" or "wide" write the long-running sets below, which take hours of
 CPU time and resume where an interrupted run stopped)
 """
 import hashlib
@@ -281,11 +281,37 @@ def main_hard():
                   flush=True)
 
 
+# Long motifs: planted (40,4), n = 20, m = 600, seed 1, from W1 (the
+# 128-bit-code oracle; motifs written as decimal integers).
+def main_wide():
+    path = os.path.join(HERE, "wide_40_4_seed1.txt")
+    if os.path.exists(path):
+        return
+    inst = pmsgen.planted(1, 20, 600, 40, 4)
+    t0 = time.time()
+    got, h = oracle.o1_wide(inst.seqs, 20, 600, 40, 4, threads=THREADS)
+    t1 = time.time()
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write("# Exact (40,4)-motif set of one synthetic planted instance,\n")
+        f.write("# written by tests/golden/make_golden.py from the CPU oracle\n")
+        f.write("# (W1, sample-driven over 128-bit codes).\n")
+        f.write("n = 20\nm = 600\nl = 40\nd = 4\nseed = 1\n")
+        f.write("input_sha256 = %s\n" % hashlib.sha256(inst.seqs).hexdigest())
+        f.write("planted = %s\n" % inst.motif.decode())
+        f.write("hcanon = %d\n" % h)
+        f.write("count = %d\n" % len(got))
+        f.write("motifs = %s\n" % ",".join(str(v) for v in got))
+        f.write("oracle_seconds = %.1f\n" % (t1 - t0))
+    os.replace(tmp, path)
+    print("wide 40 4", len(got), "h=%d %.1fs" % (h, t1 - t0), flush=True)
+
+
 if __name__ == "__main__":
     mode = sys.argv[1] if len(sys.argv) > 1 else ""
-    if mode in ("large", "batched", "served", "hard"):
+    if mode in ("large", "batched", "served", "hard", "wide"):
         {"large": main_large, "batched": main_batched,
-         "served": main_served, "hard": main_hard}[mode]()
+         "served": main_served, "hard": main_hard, "wide": main_wide}[mode]()
         sys.exit(0)
     if len(sys.argv) > 1 and sys.argv[1] == "protein":
         main_protein()

@@ -1,0 +1,166 @@
+"""GPU: long motifs (pms_solve_wide, 1 <= l <= 64, 128-bit codes) against the
+oracle W1, element by element, with the canonical Hamming-test count."""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_00306_amd as pms
+import pmsgen
+
+pytestmark = pytest.mark.gpu
+
+ACGT = b"ACGT"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def as_ints(words: np.ndarray):
+    return [(int(h) << 64) | int(lo) for h, lo in words]
+
+
+def code_of(s: bytes) -> int:
+    c = 0
+    for ch in s:
+        c = 4 * c + ACGT.index(ch)
+    return c
+
+
+def family(seed, n, m, changes):
+    """n copies of one random string with a few substitutions each."""
+    rng = random.Random(seed)
+    base = bytes(rng.choice(ACGT) for _ in range(m))
+    rows = []
+    for _ in range(n):
+        r = bytearray(base)
+        for p in rng.sample(range(m), changes):
+            r[p] = rng.choice([b for b in ACGT if b != r[p]])
+        rows.append(bytes(r))
+    return b"".join(rows)
+
+
+# (n, m, l, d, changes, seed): strings that share neighbourhoods, ragged
+# lengths, every word boundary of the planes (l = 33, 48, 63, 64)
+CASES = [
+    (3, 40, 33, 1, 1, 1), (2, 39, 33, 2, 2, 2), (4, 45, 36, 2, 2, 3),
+    (3, 52, 40, 0, 1, 4), (2, 47, 40, 3, 3, 5), (5, 60, 48, 2, 2, 6),
+    (3, 70, 57, 3, 3, 7), (2, 66, 63, 2, 2, 8), (3, 67, 64, 1, 1, 9),
+    (2, 67, 64, 3, 3, 10), (6, 100, 44, 3, 4, 11),
+]
+
+
+@pytest.mark.parametrize("n,m,l,d,changes,seed", CASES)
+def test_wide_vs_oracle(n, m, l, d, changes, seed):
+    seqs = family(seed, n, m, changes)
+    want, hw = oracle.o1_wide(seqs, n, m, l, d)
+    say("wide", n, m, l, d, seed)
+    with pms.Context() as c:
+        got = c.solve_wide(seqs, n, m, l, d)
+        st = c.stats()
+    assert as_ints(got) == want
+    assert st["hcanon"] == hw
+
+
+def test_wide_random_strings_and_plants():
+    rng = random.Random(21)
+    with pms.Context() as c:
+        for t in range(12):
+            l = rng.choice([33, 37, 41, 50, 64])
+            d = rng.randint(1, 3)
+            n = rng.randint(2, 6)
+            m = l + rng.randint(0, 40)
+            inst = pmsgen.planted(100 + t, n, m, l, d)
+            want, hw = oracle.o1_wide(inst.seqs, n, m, l, d)
+            say("wide planted", t, n, m, l, d)
+            got = c.solve_wide(inst.seqs, n, m, l, d)
+            assert as_ints(got) == want, (t, n, m, l, d)
+            assert c.stats()["hcanon"] == hw
+            assert code_of(inst.motif) in want
+
+
+def test_wide_one_string_is_the_union_of_spheres():
+    # thousands of codes: the multi-pass radix sort, not the one-group sort
+    for (m, l, d) in [(43, 40, 2), (66, 64, 2), (35, 33, 3)]:
+        rng = random.Random(m)
+        s = bytes(rng.choice(ACGT) for _ in range(m))
+        want, _ = oracle.o1_wide(s, 1, m, l, d)
+        say("wide n=1", m, l, d, len(want))
+        with pms.Context() as c:
+            got = c.solve_wide(s, 1, m, l, d)
+        assert len(want) > 4096
+        assert as_ints(got) == want
+
+
+def test_wide_short_motifs_equal_pms_solve():
+    with pms.Context() as c:
+        for (n, m, l, d, seed) in [(5, 60, 9, 2, 1), (4, 80, 13, 4, 2),
+                                   (6, 50, 16, 3, 3), (3, 45, 32, 3, 4),
+                                   (1, 12, 11, 2, 5)]:
+            inst = pmsgen.planted(seed, n, m, l, d)
+            plain = c.solve(inst.seqs, n, m, l, d)
+            wide = c.solve_wide(inst.seqs, n, m, l, d)
+            assert np.all(wide[:, 0] == 0)
+            np.testing.assert_array_equal(wide[:, 1], plain)
+
+
+def test_wide_device_entry_and_capacity():
+    import torch
+    n, m, l, d = 4, 60, 40, 2
+    seqs = family(31, n, m, 2)
+    want, _ = oracle.o1_wide(seqs, n, m, l, d)
+    assert len(want) > 2
+    dev = torch.device("cuda:0")
+    ds = torch.frombuffer(bytearray(seqs), dtype=torch.uint8).to(dev)
+    out = torch.zeros(2 * len(want), dtype=torch.int64, device=dev)
+    with pms.Context() as c:
+        with pytest.raises(pms.PmsError) as e:
+            c.solve_wide_device(ds.data_ptr(), n, m, l, d, out.data_ptr(), 2)
+        assert e.value.needed == len(want)
+        k = c.solve_wide_device(ds.data_ptr(), n, m, l, d, out.data_ptr(),
+                                len(want))
+        torch.cuda.synchronize()
+    assert k == len(want)
+    w = out.cpu().numpy().view(np.uint64).reshape(k, 2)
+    assert as_ints(w) == want
+
+
+def test_wide_errors():
+    with pms.Context() as c:
+        for (n, m, l, d) in [(1, 70, 65, 1), (1, 70, 0, 0), (1, 30, 40, 1),
+                             (1, 70, 40, 40), (1, 70, 64, 40)]:
+            with pytest.raises(pms.PmsError) as e:
+                c.solve_wide(b"A" * (n * m), n, m, l, d)
+            assert e.value.status == pms.PMS_EINVAL
+        with pytest.raises(pms.PmsError) as e:
+            c.solve_wide(b"ACGT" * 9 + b"N" + b"ACG", 1, 40, 33, 1)
+        assert e.value.status == pms.PMS_EBASE
+        assert "offset 36" in str(e.value)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden",
+                      "wide_40_4_seed1.txt")
+
+
+def test_wide_full_size_golden():
+    """Planted (40,4), n = 20, m = 600: the set stored by the oracle."""
+    kv = {}
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            k, v = [t.strip() for t in line.split("=", 1)]
+            kv[k] = v
+    inst = pmsgen.planted(1, 20, 600, 40, 4)
+    import hashlib
+    assert kv["input_sha256"] == hashlib.sha256(inst.seqs).hexdigest()
+    want = [int(x) for x in kv["motifs"].split(",") if x]
+    with pms.Context() as c:
+        got = c.solve_wide(inst.seqs, 20, 600, 40, 4)
+        st = c.stats()
+    assert as_ints(got) == want
+    assert st["hcanon"] == int(kv["hcanon"])
+    assert code_of(inst.motif) in want
