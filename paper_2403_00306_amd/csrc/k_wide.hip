@@ -15,6 +15,7 @@ namespace pms {
 
 constexpr int kWidePer = 4;                    // candidates per thread
 constexpr int kWideChunk = kTPB * kWidePer;    // sphere indexes per item
+constexpr int kWideGrab = 4;                   // items per counter update
 
 __device__ __forceinline__ int wide_base(uint8_t ch)
 {
@@ -91,12 +92,15 @@ __device__ __forceinline__ W128 wide_code(ulonglong2 c, int l)
     const uint64_t lr = __brevll(c.y) >> (64 - l);
     W128 w;
     w.lo = (spread32((uint32_t)hr) << 1) | spread32((uint32_t)lr);
-    w.hi = (spread32((uint32_t)(hr >> 32)) << 1) | spread32((uint32_t)(lr >> 32));
+    w.hi = (spread32((uint32_t)(hr >> 32)) << 1) |
+           spread32((uint32_t)(lr >> 32));
     return w;
 }
 
 // Work items are (reference l-mer x of s_1, chunk of kWideChunk sphere
-// indexes), taken from a counter by persistent workgroups.
+// indexes), taken kWideGrab at a time from a counter by persistent
+// workgroups (every workgroup updates the same counter, so fewer updates
+// keep it off the memory path).
 __global__ __launch_bounds__(kTPB) void
 k_wide_filter(WideJob J, unsigned long long *next, unsigned long long nitems)
 {
@@ -112,106 +116,111 @@ k_wide_filter(WideJob J, unsigned long long *next, unsigned long long nitems)
     for (;;) {
         __syncthreads();
         if (tid == 0)
-            s_item = atomicAdd(next, 1ull);
+            s_item = atomicAdd(next, (unsigned long long)kWideGrab);
         __syncthreads();
-        const unsigned long long it = s_item;
-        if (it >= nitems)
+        const unsigned long long it0 = s_item;
+        if (it0 >= nitems)
             break;
-        const int ref = (int)(it / per_ref);
-        const uint64_t c0 = (it % per_ref) * kWideChunk;
-        const ulonglong2 x = J.planes[ref];   // s_1 is row 0
-        ulonglong2 cp[kWidePer];
-        bool live[kWidePer];
-#pragma unroll
-        for (int u = 0; u < kWidePer; u++) {
-            const uint64_t r = c0 + (uint64_t)u * kTPB + tid;
-            live[u] = r < J.nb;
-            cp[u] = x;
-            if (!live[u])
-                continue;
-            // unrank: weight k, position set, base-3 digits in position order
-            int k = 0;
-            while (k < J.d && r >= J.cum[k + 1])
-                k++;
-            const uint64_t rr = r - J.cum[k];
-            const uint64_t pr = rr / J.pow3[k];
-            uint64_t dig = rr - pr * J.pow3[k];
-            uint64_t mask = J.posset[J.posoff[k] + pr];
-            while (mask) {
-                const int p = __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                const uint64_t delta = 1u + dig % 3u;
-                dig /= 3u;
-                cp[u].x ^= (delta >> 1) << p;
-                cp[u].y ^= (delta & 1u) << p;
-            }
-        }
-        // strings s_2..s_n in order, early exit per string and per wave
-        for (int i = 1; i < J.n; i++) {
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < kWidePer; u++)
-                any |= live[u];
-            if (__ballot(any) == 0)
-                break;
-            const c_u64 *row = (const c_u64 *)(const void *)(
-                J.planes + (size_t)i * J.L);
-            // running minimum distance per candidate; a dead candidate
-            // starts at 0 so that it never holds the wave back
-            uint32_t mind[kWidePer];
+        const unsigned long long it1 =
+            min(it0 + (unsigned long long)kWideGrab, nitems);
+        for (unsigned long long it = it0; it < it1; it++) {
+            const int ref = (int)(it / per_ref);
+            const uint64_t c0 = (it % per_ref) * kWideChunk;
+            const ulonglong2 x = J.planes[ref];   // s_1 is row 0
+            ulonglong2 cp[kWidePer];
+            bool live[kWidePer];
 #pragma unroll
             for (int u = 0; u < kWidePer; u++) {
-                mind[u] = live[u] ? 255u : 0u;
-                hc += live[u] ? (unsigned long long)J.L : 0ull;
-            }
-            int y0 = 0;
-            for (; y0 + 8 <= J.L; y0 += 8) {
-#pragma unroll
-                for (int y = 0; y < 8; y += 2) {
-                    const uint64_t ah = row[2 * (y0 + y)];
-                    const uint64_t al = row[2 * (y0 + y) + 1];
-                    const uint64_t bh = row[2 * (y0 + y) + 2];
-                    const uint64_t bl = row[2 * (y0 + y) + 3];
-#pragma unroll
-                    for (int u = 0; u < kWidePer; u++)
-                        mind[u] = min(mind[u], min(dist64(cp[u], ah, al),
-                                                   dist64(cp[u], bh, bl)));
+                const uint64_t r = c0 + (uint64_t)u * kTPB + tid;
+                live[u] = r < J.nb;
+                cp[u] = x;
+                if (!live[u])
+                    continue;
+                // unrank: weight k, position set, base-3 digits in
+                // position order
+                int k = 0;
+                while (k < J.d && r >= J.cum[k + 1])
+                    k++;
+                const uint64_t rr = r - J.cum[k];
+                const uint64_t pr = rr / J.pow3[k];
+                uint64_t dig = rr - pr * J.pow3[k];
+                uint64_t mask = J.posset[J.posoff[k] + pr];
+                while (mask) {
+                    const int p = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    const uint64_t delta = 1u + dig % 3u;
+                    dig /= 3u;
+                    cp[u].x ^= (delta >> 1) << p;
+                    cp[u].y ^= (delta & 1u) << p;
                 }
-                bool done = true;
+            }
+            // strings s_2..s_n in order, early exit per string and per wave
+            for (int i = 1; i < J.n; i++) {
+                bool any = false;
 #pragma unroll
                 for (int u = 0; u < kWidePer; u++)
-                    done &= mind[u] <= dd;
-                if (__all(done))
+                    any |= live[u];
+                if (__ballot(any) == 0)
                     break;
-            }
-            if (y0 + 8 > J.L) {
-                for (int y = y0; y < J.L; y++) {
-                    const uint64_t ah = row[2 * y], al = row[2 * y + 1];
+                const c_u64 *row = (const c_u64 *)(const void *)(
+                    J.planes + (size_t)i * J.L);
+                // running minimum distance per candidate; a dead candidate
+                // starts at 0 so that it never holds the wave back
+                uint32_t mind[kWidePer];
+#pragma unroll
+                for (int u = 0; u < kWidePer; u++) {
+                    mind[u] = live[u] ? 255u : 0u;
+                    hc += live[u] ? (unsigned long long)J.L : 0ull;
+                }
+                int y0 = 0;
+                for (; y0 + 8 <= J.L; y0 += 8) {
+#pragma unroll
+                    for (int y = 0; y < 8; y += 2) {
+                        const uint64_t ah = row[2 * (y0 + y)];
+                        const uint64_t al = row[2 * (y0 + y) + 1];
+                        const uint64_t bh = row[2 * (y0 + y) + 2];
+                        const uint64_t bl = row[2 * (y0 + y) + 3];
+#pragma unroll
+                        for (int u = 0; u < kWidePer; u++)
+                            mind[u] = min(mind[u], min(dist64(cp[u], ah, al),
+                                                       dist64(cp[u], bh, bl)));
+                    }
+                    bool done = true;
 #pragma unroll
                     for (int u = 0; u < kWidePer; u++)
-                        mind[u] = min(mind[u], dist64(cp[u], ah, al));
+                        done &= mind[u] <= dd;
+                    if (__all(done))
+                        break;
                 }
+                if (y0 + 8 > J.L) {
+                    for (int y = y0; y < J.L; y++) {
+                        const uint64_t ah = row[2 * y], al = row[2 * y + 1];
+#pragma unroll
+                        for (int u = 0; u < kWidePer; u++)
+                            mind[u] = min(mind[u], dist64(cp[u], ah, al));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kWidePer; u++)
+                    live[u] &= mind[u] <= dd;
             }
+            // a motif is kept from the first l-mer of s_1 within d of it only
+            const c_u64 *row0 = (const c_u64 *)(const void *)J.planes;
 #pragma unroll
-            for (int u = 0; u < kWidePer; u++)
-                live[u] &= mind[u] <= dd;
-        }
-        // a motif is kept from the first l-mer of s_1 within d of it only
-        const c_u64 *row0 = (const c_u64 *)(const void *)J.planes;
-#pragma unroll
-        for (int u = 0; u < kWidePer; u++) {
-            if (!live[u])
-                continue;
-            for (int j = 0; j < ref; j++)
-                if (dist64(cp[u], row0[2 * j], row0[2 * j + 1]) <= dd) {
-                    live[u] = false;
-                    break;
-                }
-            if (!live[u])
-                continue;
-            const unsigned long long at = atomicAdd(J.heap_top, 1ull);
-            if (at < J.heap_cap)
-                J.heap[at] = wide_code(cp[u], J.l);
+            for (int u = 0; u < kWidePer; u++) {
+                if (!live[u])
+                    continue;
+                for (int j = 0; j < ref; j++)
+                    if (dist64(cp[u], row0[2 * j], row0[2 * j + 1]) <= dd) {
+                        live[u] = false;
+                        break;
+                    }
+                if (!live[u])
+                    continue;
+                const unsigned long long at = atomicAdd(J.heap_top, 1ull);
+                if (at < J.heap_cap)
+                    J.heap[at] = wide_code(cp[u], J.l);
+            }
         }
     }
     if (hc)

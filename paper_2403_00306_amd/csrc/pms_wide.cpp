@@ -127,7 +127,8 @@ int wide_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs, int n,
         if ((rc = c->alloc(c->aux, aoff)))
             return rc;
         char *base = (char *)c->arena.p, *abase = (char *)c->aux.p;
-        const uint8_t *seqs = d_seqs ? d_seqs : (const uint8_t *)(base + o_seqs);
+        const uint8_t *seqs =
+            d_seqs ? d_seqs : (const uint8_t *)(base + o_seqs);
         unsigned long long *bad = (unsigned long long *)(base + o_bad);
         unsigned long long *next = (unsigned long long *)(base + o_cnt);
         unsigned long long *top = next + 1;
