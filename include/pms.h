@@ -237,8 +237,9 @@ int pms_solve_alphabet_device(pms_ctx *ctx, const char *alphabet, int sigma,
  * l-mers, strings tested in order with early exit, each motif kept from the
  * first l-mer of s_1 within d of it), then sorts on the device. The words
  * belong to the context as for pms_solve. Errors as pms_solve, with the
- * domain 1 <= l <= 64; PMS_EINVAL also for a sphere beyond 2^62 candidates
- * or 2^22 position sets. For l <= 32 the low words are pms_solve's codes.
+ * domain 1 <= l <= 64; PMS_EINVAL also for a sphere beyond 2^62 candidates,
+ * 2^22 position sets, or more than 2^62 candidates over all m-l+1
+ * references. For l <= 32 the low words are pms_solve's codes.
  */
 int pms_solve_wide(pms_ctx *ctx, const char *seqs, int n, int m, int l,
                    int d, const uint64_t **motifs, size_t *count);

@@ -93,6 +93,10 @@ int wide_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs, int n,
     if (!plan_wide(l, d, P))
         return c->fail(PMS_EINVAL, "sphere of (%d,%d) too large", l, d);
     const int L = m - l + 1;
+    // candidates (sphere x references) must stay countable in 64 bits
+    if ((unsigned __int128)P.nb * (unsigned)L > (((unsigned __int128)1) << 62))
+        return c->fail(PMS_EINVAL, "%llu candidates per reference x %d "
+                       "references: too many", (unsigned long long)P.nb, L);
     const auto shape_key = std::make_tuple(n, m, l, d, -1000);
     uint64_t heap_cap = 1 << 16;
     {
