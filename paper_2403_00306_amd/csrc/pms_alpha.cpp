@@ -120,6 +120,11 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
     while ((1 << planes) < sigma)
         planes++;
     const int L = m - l + 1;
+    // candidates (sphere x references) must stay countable in 64 bits
+    if ((unsigned __int128)P.nb * (unsigned)L > (((unsigned __int128)1) << 62))
+        return c->fail(PMS_EINVAL, "alphabet: %llu candidates per reference "
+                       "x %d references: too many", (unsigned long long)P.nb,
+                       L);
 
     const auto shape_key = std::make_tuple(n, m, l, d, -sigma);
     uint64_t heap_cap = 1 << 16;
