@@ -211,8 +211,9 @@ int pms_solve_quorum_device(pms_ctx *ctx, const uint8_t *d_seqs, int n,
  * exit), then sorts and drops repeats on the device. Output as pms_solve.
  * PMS_EBASE for a byte outside the alphabet; PMS_EINVAL for a bad shape, a
  * bad alphabet, sigma^l above 2^64 (codes past 64 bits; 2^64 itself, as
- * 16^16, is allowed) or a sphere beyond 2^62 candidates
- * (or 2^22 position sets). alphabet "ACGT" with sigma 4 is pms_solve.
+ * 16^16, is allowed), a sphere beyond 2^62 candidates (or 2^22 position
+ * sets) or more than 2^62 candidates over all m-l+1 references. alphabet
+ * "ACGT" with sigma 4 is pms_solve.
  */
 int pms_solve_alphabet(pms_ctx *ctx, const char *alphabet, int sigma,
                        const char *seqs, int n, int m, int l, int d,
