@@ -52,6 +52,8 @@ CASES = [
     (3, 52, 40, 0, 1, 4), (2, 47, 40, 3, 3, 5), (5, 60, 48, 2, 2, 6),
     (3, 70, 57, 3, 3, 7), (2, 66, 63, 2, 2, 8), (3, 67, 64, 1, 1, 9),
     (2, 67, 64, 3, 3, 10), (6, 100, 44, 3, 4, 11),
+    # many strings; one l-mer per string at the longest l; one string, d = 0
+    (70, 45, 40, 2, 1, 12), (3, 64, 64, 2, 1, 13), (1, 64, 64, 0, 0, 14),
 ]
 
 
