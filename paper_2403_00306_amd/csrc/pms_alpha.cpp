@@ -280,7 +280,7 @@ int alpha_core(pms_ctx *c, const char *alphabet, int sigma,
         S.main_launches = 1;
         S.ms_total = now_ms() - t0;
         c->last = S;
-        c->last_L = L;
+        c->last_L = 0;   // no per-reference counts on this path
         res->d_out = dst;
         res->count = total;
         return PMS_OK;

@@ -843,7 +843,8 @@ int solve_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs,
         }
         S.ms_total = now_ms() - t0;
         c->last = S;
-        c->last_L = L;
+        // per-reference counts exist after the plain filter path only
+        c->last_L = quorum_filter ? 0 : L;
         return PMS_OK;
     }
     return c->fail(PMS_ENOMEM, "output did not fit after retries");

@@ -227,7 +227,7 @@ int wide_core(pms_ctx *c, const char *host_seqs, const uint8_t *d_seqs, int n,
         S.main_launches = 1;
         S.ms_total = now_ms() - t0;
         c->last = S;
-        c->last_L = L;
+        c->last_L = 0;   // no per-reference counts on this path
         res->d_out = dst;
         res->count = found;
         return PMS_OK;

@@ -166,3 +166,15 @@ def test_wide_full_size_golden():
     assert as_ints(got) == want
     assert st["hcanon"] == int(kv["hcanon"])
     assert code_of(inst.motif) in want
+
+
+def test_wide_leaves_no_per_reference_counts():
+    # per-reference test counts come from the plain filter path only; a
+    # long-motif solve must not expose the previous solve's counts
+    inst = pmsgen.planted(3, 5, 60, 12, 2)
+    with pms.Context(path=pms.PATH_FILTER) as c:
+        c.solve(inst.seqs, 5, 60, 12, 2)
+        assert len(c.hcanon_per_ref(49)) == 49
+        c.solve_wide(inst.seqs, 5, 60, 12, 2)
+        with pytest.raises(pms.PmsError):
+            c.hcanon_per_ref(49)
