@@ -394,8 +394,10 @@ int pms_serve_stats_get(const pms_ctx *ctx, pms_serve_stats *out);
 
 /*
  * Filter path only: copy the per-reference Hamming-test counts of the last
- * filter-path solve (entry j: the tests spent on candidates from the l-mer
- * of s_1 at offset j). n_refs must be m-l+1 of that solve.
+ * solve, when it ran the plain (q = n) filter path (entry j: the tests spent
+ * on candidates from the l-mer of s_1 at offset j). n_refs must be m-l+1 of
+ * that solve; PMS_EINVAL otherwise, and after any solve on another path
+ * (tiled, bitset, pair, quorum, another alphabet, long motifs).
  */
 int pms_last_hcanon_per_ref(const pms_ctx *ctx, uint64_t *out, size_t n_refs);
 
