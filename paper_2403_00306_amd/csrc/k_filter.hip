@@ -269,7 +269,9 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
                     atomicAdd(&sh.hc[ref[k] - x_first], (uint32_t)L);
             }
             // after compaction the live candidates fill slots 0..kk-1: scan
-            // only those
+            // only those (3 and 6 slots as well as powers of two: after the
+            // first string about a third of a block is live, 3 of the 8
+            // slots, which a 4-slot scan would pad by a third)
             const int kk = (nlive + kTPB - 1) / kTPB;
             if (__any(live != 0)) {
                 if (kk <= 1)
@@ -278,8 +280,14 @@ k_filter(const InstDev *inst, const uint2 *masks, uint64_t nb,
                 else if (kk <= 2)
                     hexec += 2ull * (unsigned long long)scan_string<2>(
                         yp, L, c, mind, d, live);
+                else if (kk <= 3)
+                    hexec += 3ull * (unsigned long long)scan_string<3>(
+                        yp, L, c, mind, d, live);
                 else if (kk <= 4)
                     hexec += 4ull * (unsigned long long)scan_string<4>(
+                        yp, L, c, mind, d, live);
+                else if (kk <= 6)
+                    hexec += 6ull * (unsigned long long)scan_string<6>(
                         yp, L, c, mind, d, live);
                 else
                     hexec += (unsigned long long)kFPer *
