@@ -4,8 +4,9 @@ Calls only the CPU oracle (both O1 and the brute force O0, which must agree)
 on inputs from the seeded generator; nothing here touches the GPU library.
 Run from the repository root:  python tests/golden/make_golden.py
 (add "quorum" or "protein" to write only those files; "large", "batched",
-"served", "hard" or "wide" write the long-running sets below, which take hours of
-CPU time and resume where an interrupted run stopped)
+"served", "served_refs", "hard" or "wide" write the long-running sets
+below, which take hours of CPU time and resume where an interrupted run
+stopped)
 """
 import hashlib
 import os
@@ -281,6 +282,57 @@ def main_hard():
                   flush=True)
 
 
+# Every (19,7) request of the served stream: the motifs O1 derives from two
+# reference l-mers of s_1 (the plant's offset and one seeded other), each a
+# subset of the request's motif set. A whole (19,7) set takes about an hour
+# and a half of eight cores, a single reference about a minute of one.
+def main_served_refs():
+    import concurrent.futures as cf
+    import random
+    reqs = pmsgen.served(seed=11, count=2000)
+    path = os.path.join(HERE, "served_seed11_refs.txt")
+    done = set()
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                done.add((int(t[0]), int(t[3])))
+    else:
+        with open(path, "w") as f:
+            f.write("# Motifs that the CPU oracle O1 derives from single reference\n"
+                    "# l-mers of s_1 (offset j) of the (19,7) requests of\n"
+                    "# pmsgen.served(seed=11, count=2000): each list is a subset\n"
+                    "# of the request's motif set. Written by\n"
+                    "# tests/golden/make_golden.py.\n"
+                    "# index l d j input_sha256 hcanon_of_j count codes\n")
+    jobs = []
+    for r in reqs:
+        x = r.inst
+        if (x.l, x.d) != (19, 7):
+            continue
+        L = x.m - x.l + 1
+        others = [j for j in range(L) if j != x.positions[0]]
+        for j in [x.positions[0],
+                  random.Random(2000 + r.index).choice(others)]:
+            if (r.index, j) not in done:
+                jobs.append((r.index, x, j))
+
+    def one(job):
+        idx, x, j = job
+        got, h = oracle.o1(x.seqs, x.n, x.m, x.l, x.d, ref_begin=j,
+                           ref_end=j + 1, threads=1)
+        return idx, x, j, got, h
+
+    with cf.ThreadPoolExecutor(max_workers=int(
+            os.environ.get("GOLDEN_WORKERS", "4"))) as ex:
+        for idx, x, j, got, h in ex.map(one, jobs):
+            with open(path, "a") as f:
+                f.write("%d %d %d %d %s %d %d %s\n" % (
+                    idx, x.l, x.d, j, hashlib.sha256(x.seqs).hexdigest(), h,
+                    len(got), ",".join(str(int(v)) for v in got) or "none"))
+            print("served refs", idx, j, len(got), flush=True)
+
+
 # Long motifs: planted (40,4), n = 20, m = 600, seed 1, from W1 (the
 # 128-bit-code oracle; motifs written as decimal integers).
 def main_wide():
@@ -309,9 +361,10 @@ def main_wide():
 
 if __name__ == "__main__":
     mode = sys.argv[1] if len(sys.argv) > 1 else ""
-    if mode in ("large", "batched", "served", "hard", "wide"):
+    if mode in ("large", "batched", "served", "hard", "wide", "served_refs"):
         {"large": main_large, "batched": main_batched,
-         "served": main_served, "hard": main_hard, "wide": main_wide}[mode]()
+         "served": main_served, "hard": main_hard, "wide": main_wide,
+         "served_refs": main_served_refs}[mode]()
         sys.exit(0)
     if len(sys.argv) > 1 and sys.argv[1] == "protein":
         main_protein()

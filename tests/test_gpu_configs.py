@@ -10,7 +10,9 @@ and of a seeded 10% sample of the (15,5) and (17,6) requests (then of
 the (19,7) ones, as the oracle finishes them): its size, the hash of its
 codes and, when short, the codes. Every stored instance is compared;
 served requests without a stored set are checked code by code with the
-direct motif check (Definition 5) and must hold the plant.
+direct motif check (Definition 5) and must hold the plant; every (19,7)
+request must also hold the motifs that the oracle derives from two of its
+reference l-mers.
 """
 import hashlib
 import os
@@ -124,3 +126,25 @@ def test_served_config_vs_oracle():
         assert plant_code(x) in set(int(v) for v in got), r.index
     say("served: %d of %d requests compared with oracle sets" %
         (checked, len(reqs)))
+    # every (19,7) request: the motifs the oracle derives from two of its
+    # reference l-mers (the plant's and a seeded other) are all served
+    refs = read_refs("served_seed11_refs.txt")
+    n19 = sum(1 for r in reqs if (r.inst.l, r.inst.d) == (19, 7))
+    assert len({i for i, *_ in refs}) == n19
+    for idx, l, d, sha, codes in refs:
+        x = reqs[idx].inst
+        assert (x.l, x.d) == (l, d)
+        assert hashlib.sha256(x.seqs).hexdigest() == sha
+        assert set(codes) <= set(int(v) for v in res[idx]), idx
+
+
+def read_refs(name):
+    """(index, l, d, input_sha, codes) per stored reference."""
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        if not line.strip() or line.startswith("#"):
+            continue
+        t = line.split()
+        codes = [] if t[7] == "none" else [int(v) for v in t[7].split(",")]
+        out.append((int(t[0]), int(t[1]), int(t[2]), t[4], codes))
+    return out
