@@ -224,6 +224,31 @@ def oracle_checked(np, name: str, insts, results) -> dict:
             "fraction_checked": checked / max(1, len(insts))}
 
 
+def oracle_refs_checked(name: str, insts, results) -> dict:
+    """Requests with stored reference subsets (tests/golden/<name>: index l
+    d j input_sha hcanon count codes, the motifs the oracle derives from one
+    reference l-mer of s_1): each subset must lie in the served set."""
+    import hashlib
+    per = {}
+    try:
+        for line in open(os.path.join(GOLDEN, name)):
+            if not line.strip() or line.startswith("#"):
+                continue
+            t = line.split()
+            codes = [] if t[7] == "none" else [int(v) for v in t[7].split(",")]
+            per.setdefault(int(t[0]), []).append((t[4], codes))
+    except OSError:
+        return {"file": "tests/golden/" + name, "requests": 0, "matched": 0}
+    matched = 0
+    for i, subsets in per.items():
+        x, got = insts[i], set(int(v) for v in results[i])
+        matched += all(hashlib.sha256(x.seqs).hexdigest() == sha and
+                       set(codes) <= got for sha, codes in subsets)
+    return {"file": "tests/golden/" + name, "requests": len(per),
+            "references": sum(len(v) for v in per.values()),
+            "matched": matched}
+
+
 def batch_bench(pms, pmsgen, np, tune: bool) -> dict:
     """256 independent instances: one pms_solve_batch call (one persistent
     launch, replayed as a HIP graph) vs the same instances solved one by
@@ -500,7 +525,9 @@ def serve_bench(pms, pmsgen, np, count: int, launch_ms: float = 0.0) -> dict:
             "launch_ms_target": launch_ms or None,
             "mix_equals_saturated_and_alone": bool(same and alone_ok),
             "oracle_checked": oracle_checked(
-                np, "served_seed11.txt", [r.inst for r in reqs], res)}
+                np, "served_seed11.txt", [r.inst for r in reqs], res),
+            "oracle_refs_checked": oracle_refs_checked(
+                "served_seed11_refs.txt", [r.inst for r in reqs], res)}
 
 
 def main():
