@@ -477,12 +477,17 @@ k_filter_quorum(const InstDev *inst, const uint2 *masks, uint64_t nb, int R,
             }
             const int kk = (nlive + kTPB - 1) / kTPB;
             if (__any(test != 0)) {
+                // slot counts as in k_filter
                 if (kk <= 1)
                     scan_string<1>(yp, L, c, mind, d, test);
                 else if (kk <= 2)
                     scan_string<2>(yp, L, c, mind, d, test);
+                else if (kk <= 3)
+                    scan_string<3>(yp, L, c, mind, d, test);
                 else if (kk <= 4)
                     scan_string<4>(yp, L, c, mind, d, test);
+                else if (kk <= 6)
+                    scan_string<6>(yp, L, c, mind, d, test);
                 else
                     scan_string<kFPer>(yp, L, c, mind, d, test);
             }
